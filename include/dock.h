@@ -1,0 +1,203 @@
+/*
+ * dock.h -- C ABI of the MI355X (gfx950) geometric-docking library.
+ *
+ * The library docks ligands into a rigid pocket with the greedy multi-restart
+ * method of Alg. 1 in Vitali et al., "Exploring the trade-off between latency
+ * and batched GPU implementations of a virtual screening application"
+ * (arXiv:2209.05069), Section "Application Description":
+ *   for each ligand and each restart r:
+ *     Generate_Starting_Pose: the ligand, centred on its centroid, is turned by
+ *       the r-th start orientation and placed at the grid centre;
+ *     Alignment (rigid rotation): of the A*A orientations R_y(2 pi j/A) R_x(2 pi i/A)
+ *       about the pose centroid the best-scoring one is applied
+ *       (orientation index o = i*A + j; the first maximum wins);
+ *     Optimize Pose: for sweep_passes passes, for each rotatable bond in the
+ *       given order, of the torsion_steps rotations by 2 pi k/T of the bond's
+ *       moving fragment about the bond axis, those with an intramolecular bump
+ *       are rejected and the best-scoring remaining one is applied (the first
+ *       maximum wins; k = 0 keeps the conformation);
+ *   Select Poses: restarts by score (ties: lower restart), a pose is kept unless
+ *     its plain RMSD to an already kept pose is below dedup_rmsd, at most top_k;
+ *   final step: the alignment again on each kept pose (if final_align), then its
+ *     score; outputs ordered by final score (ties: lower restart).
+ * Score of a pose = sum over atoms of the trilinearly interpolated score grid of
+ * the atom's type (grid coordinates clamped to the box); higher is better.
+ * Bump = a pair with one atom moving and one not, at least bump_min_bonds bonds
+ * apart, closer than bump_dist.
+ * The paper's chemical rescoring (Rescore Pose) is not part of this library: its
+ * function is not given in the paper; the final step above stands in for it.
+ *
+ * All entry points return a dock_status value and never throw.  On failure,
+ * dock_last_error() returns a message for the calling thread.
+ * A context is bound to one device.  Its entry points may be called from
+ * several host threads; calls that use the same stream are serialised by that
+ * stream, and each stream gets its own workspace.
+ */
+#ifndef DOCK_H
+#define DOCK_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct dock_ctx dock_ctx;
+
+typedef enum {
+    DOCK_OK = 0,
+    DOCK_EINVAL = -1,   /* bad argument (message says which) */
+    DOCK_ENOMEM = -2,   /* device or host allocation failed */
+    DOCK_EAGAIN = -3,   /* dock_submit: not enough free device memory now; retry later */
+    DOCK_ENOENT = -4,   /* unknown pocket id or ticket */
+    DOCK_EDEVICE = -5,  /* HIP runtime error (message has the HIP error string) */
+    DOCK_EBUSY = -6     /* pocket still used by submitted work */
+} dock_status;
+
+/* Per-ligand status written to dock_results.status.  A ligand that fails a
+ * check is not docked; its outputs are n_poses = 0 and best_score = -inf. */
+typedef enum {
+    DOCK_LIG_OK = 0,
+    DOCK_LIG_BAD_SIZE = 1,   /* atoms not in [1, DOCK_MAX_ATOMS], rotatable bonds > DOCK_MAX_ROT,
+                                or bonds > 8 * atoms */
+    DOCK_LIG_BAD_TYPE = 2,   /* atom type >= pocket ntypes */
+    DOCK_LIG_BAD_BOND = 3,   /* bond or rotatable bond atom index out of range / self bond */
+    DOCK_LIG_BAD_MASK = 4,   /* moving mask is not the fragment the bond cuts off, or the bond
+                                is in a ring, or the ligand is not connected */
+    DOCK_LIG_BAD_OFFSETS = 5 /* CSR offsets decreasing or past the declared totals */
+} dock_ligand_status;
+
+#define DOCK_MAX_ATOMS 256
+#define DOCK_MAX_ROT 64
+#define DOCK_MAX_TORSION_STEPS 1024
+#define DOCK_MAX_ALIGN_STEPS 255
+#define DOCK_MAX_TOP_K 64
+#define DOCK_TRACE_NONE 0xFFFFu /* torsion decision where every candidate bumped */
+
+/* Create a context on HIP device `device` (its index as hipSetDevice takes it). */
+int dock_create(int device, dock_ctx **out);
+/* Wait for all submitted work, free every device buffer of the context. */
+int dock_destroy(dock_ctx *ctx);
+/* Message of the calling thread's last failure ("" if none).  Valid until the
+ * thread's next call into the library. */
+const char *dock_last_error(void);
+
+/* Pocket score grids (paper: the pocket is read-only and shared by all work on a
+ * GPU; Latency Implementation subsection).  Grid point (i,j,k) of type t holds
+ * values[((t*nz + k)*ny + j)*nx + i] at position origin + spacing*(i,j,k), Angstrom.
+ * Requires ntypes in [1,255], nx,ny,nz >= 2, spacing > 0, nx*ny*nz < 2^24 and
+ * all grids together under 4 GiB.
+ * `values` is host memory; it is copied before the call returns. */
+typedef struct {
+    int32_t ntypes, nx, ny, nz;
+    float spacing;
+    float origin[3];
+    const float *values;
+} dock_grid_desc;
+
+int dock_pocket_load(dock_ctx *ctx, const dock_grid_desc *grid, int32_t *pocket_id);
+/* DOCK_EBUSY while dock_submit work that uses the pocket is not finished. */
+int dock_pocket_unload(dock_ctx *ctx, int32_t pocket_id);
+
+/* Ligand library in CSR form (paper: coordinates, atom types and the fragments
+ * of the rotatable bonds; Batched Implementation subsection).  Ligand l owns
+ * atoms [atom_off[l], atom_off[l+1]), bonds [bond_off[l], bond_off[l+1]) and
+ * rotatable bonds [rot_off[l], rot_off[l+1]); atom indices inside bonds are
+ * local to the ligand.  rot_bond[r] = (a, b): a stays, b moves; the sweep visits
+ * the rotatable bonds in this order.  rot_mask[r*mask_words + w] bit i (i = 64w +
+ * bit) is set when atom i moves with bond r (the fragment on b's side).
+ * For dock_ligands_batch every pointer is DEVICE memory; for dock_submit every
+ * pointer is HOST memory.  The totals are host values and must equal
+ * atom_off[L], bond_off[L] and rot_off[L]. */
+typedef struct {
+    int32_t n_ligands;
+    int32_t mask_words;        /* >= ceil(max atoms / 64), <= 4 */
+    int64_t n_atoms_total;
+    int64_t n_bonds_total;
+    int64_t n_rot_total;
+    const int32_t *atom_off;   /* [n_ligands+1] */
+    const float *xyz;          /* [n_atoms_total][3], Angstrom, any frame */
+    const uint8_t *type;       /* [n_atoms_total] */
+    const int32_t *bond_off;   /* [n_ligands+1] */
+    const int32_t *bond;       /* [n_bonds_total][2] */
+    const int32_t *rot_off;    /* [n_ligands+1] */
+    const int32_t *rot_bond;   /* [n_rot_total][2] */
+    const uint64_t *rot_mask;  /* [n_rot_total][mask_words] */
+} dock_library;
+
+enum { DOCK_MODE_BATCHED = 0, DOCK_MODE_PLAIN = 1 };
+
+/* Search settings.  start_quat is HOST memory, [restarts][4] quaternions
+ * (w,x,y,z) (normalised by the library), copied during the call; restart r
+ * of every ligand starts from orientation r.
+ * mode: DOCK_MODE_BATCHED docks many ligands per launch (one wavefront per
+ * (ligand, restart)); DOCK_MODE_PLAIN docks one ligand per launch sequence,
+ * spreading that ligand over the whole GPU (the paper's latency form). */
+typedef struct {
+    int32_t restarts;          /* R in [1, 4096] */
+    int32_t torsion_steps;     /* T in [1, DOCK_MAX_TORSION_STEPS] */
+    int32_t sweep_passes;      /* P in [0, 16] */
+    int32_t align_steps;       /* A in [1, DOCK_MAX_ALIGN_STEPS] */
+    int32_t top_k;             /* K in [1, DOCK_MAX_TOP_K] */
+    int32_t final_align;       /* 0 or 1 */
+    int32_t bump_min_bonds;    /* >= 1; pairs closer in bonds are never checked */
+    int32_t mode;              /* DOCK_MODE_* */
+    float bump_dist;           /* Angstrom, >= 0 */
+    float dedup_rmsd;          /* Angstrom, >= 0 (0: plain top-K) */
+    const float *start_quat;   /* HOST [restarts][4] */
+} dock_params;
+
+/* Outputs.  Same memory kind as the library (device for dock_ligands_batch,
+ * host for dock_submit).  Required: best_score, n_poses, status, pose_score,
+ * pose_restart, pose_xyz.  Optional (NULL to skip): restart_score, trace,
+ * final_trace.
+ *   pose_score[l*K + s], pose_restart[l*K + s], final_trace[l*K + s] for the
+ *     s-th output pose (s < n_poses[l]; later slots get -inf / -1 / 0);
+ *   pose_xyz: ligand l's pose s starts at float index 3*(atom_off[l]*K + s*n_l)
+ *     (slots s >= n_poses[l] are zero);
+ *   restart_score[l*R + r]: score of restart r after its sweeps;
+ *   trace: decisions of every restart, ligand l's block starts at
+ *     R*(l + P*rot_off[l]) and holds, per restart, 1 + P*B_l entries: the
+ *     alignment index o, then the applied torsion step of each decision
+ *     (DOCK_TRACE_NONE when every candidate bumped);
+ *   final_trace[l*K + s]: alignment index of the final step (0 if final_align=0).
+ * For a ligand whose status is not DOCK_LIG_OK only best_score (-inf), n_poses
+ * (0), status, pose_score (-inf), pose_restart (-1) and final_trace (0) are
+ * written; its pose_xyz, restart_score and trace entries are left as they were. */
+typedef struct {
+    float *best_score;        /* [L] */
+    int32_t *n_poses;         /* [L] */
+    int32_t *status;          /* [L] dock_ligand_status */
+    float *pose_score;        /* [L*K] */
+    int32_t *pose_restart;    /* [L*K] */
+    float *pose_xyz;          /* [n_atoms_total*K*3] */
+    float *restart_score;     /* [L*R] or NULL */
+    uint16_t *trace;          /* [R*(L + P*n_rot_total)] or NULL */
+    uint16_t *final_trace;    /* [L*K] or NULL */
+} dock_results;
+
+/* Dock a device-resident library; all work is enqueued on `stream` (a
+ * hipStream_t, NULL = the null stream) and the call returns after enqueueing.
+ * Results are valid once the stream reaches this point.  The library and the
+ * results must stay allocated until then.  Internal workspace is allocated on
+ * first use and kept per stream; growing it waits for that stream. */
+int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
+                       const dock_params *params, dock_results *out, void *stream);
+
+/* Asynchronous form on host memory (paper: the batched form's asynchronous
+ * interface, Batched Implementation subsection).  The library and params are
+ * copied before the call returns; `out` must stay valid until dock_poll reports
+ * done (or dock_wait returns).  Admission: DOCK_EAGAIN when the request does not
+ * fit in the device memory left free (less a reserve); retry after polling. */
+int dock_submit(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
+                const dock_params *params, dock_results *out, uint64_t *ticket);
+/* *done = 1 once the results of `ticket` are in `out` (the ticket is then
+ * retired; polling it again gives DOCK_ENOENT). */
+int dock_poll(dock_ctx *ctx, uint64_t ticket, int32_t *done);
+/* Block until `ticket` is done, then retire it. */
+int dock_wait(dock_ctx *ctx, uint64_t ticket);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DOCK_H */

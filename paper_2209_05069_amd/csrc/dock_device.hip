@@ -1,0 +1,1090 @@
+// dock_device.hip -- gfx950 kernels of the geometric-docking hot path.
+//
+// Method: Alg. 1 of arXiv:2209.05069 (Application Description).  One
+// wavefront docks one (ligand, restart): Generate_Starting_Pose, the A*A rigid
+// alignment and the greedy torsion sweep (Optimize Pose).  A second kernel does
+// Select Poses and the final rigid step per ligand.  Mapping choices for CDNA4:
+//  * lanes hold atoms (atom i = lane + 64*slot) for every per-atom update, so a
+//    pose lives in registers; a wave-uniform atom is fetched with readlane;
+//  * the alignment spreads the A*A orientations over the 64 lanes, and the
+//    torsion step spreads the T candidates over the lanes (T/64 per lane); each
+//    lane scores its candidates over the moving atoms, whose rotation frames
+//    sit once per wave in LDS (broadcast reads);
+//  * only the moving fragment's score changes with the torsion angle, so the
+//    candidates are ranked by that partial sum (same argmax as the full score);
+//  * best-first bump check: the wave takes the best-scoring candidate (64-bit
+//    key max: order-preserving score bits, then the lower index), checks its
+//    moving-vs-static pairs with lanes over static atoms and a ballot after each
+//    moving atom (early exit), and on a bump drops that candidate and repeats.
+//    This selects exactly the best bump-free candidate;
+//  * grid gathers are raw buffer loads: one 32-bit voffset for the cell and the
+//    8 corners as scalar offsets, with the range checked by hardware;
+//  * a persistent grid pops (ligand, restart-group) items from a per-bin queue;
+//    the ligand's coordinates, bump-pair rows and masks are staged once per
+//    item in LDS and shared by the workgroup's waves.
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "dock_internal.h"
+
+namespace dockgpu {
+
+typedef unsigned long long u64;
+
+// ---------------------------------------------------------------------------
+// wavefront helpers
+__device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
+
+__device__ __forceinline__ float wave_sum(float v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_max_u64(u64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        u64 w = __shfl_xor(v, o, 64);
+        v = w > v ? w : v;
+    }
+    return v;
+}
+
+__device__ __forceinline__ u64 wave_or_u64(u64 v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
+
+__device__ __forceinline__ float read_lane(float v, int lane) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), lane));
+}
+
+// Order-preserving map of a float to uint32 (larger float -> larger integer).
+__device__ __forceinline__ uint32_t ord_f32(float f) {
+    uint32_t u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float unord_f32(uint32_t u) {
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+// Key of (score, index): the max key has the best score, then the lowest index.
+__device__ __forceinline__ u64 make_key(float s, uint32_t idx) {
+    return ((u64)ord_f32(s) << 32) | (u64)(0xFFFFFFFFu - idx);
+}
+__device__ __forceinline__ uint32_t key_index(u64 k) { return 0xFFFFFFFFu - (uint32_t)k; }
+__device__ __forceinline__ float key_score(u64 k) { return unord_f32((uint32_t)(k >> 32)); }
+
+// Make LDS writes of this wave visible to its own later LDS reads by other lanes.
+__device__ __forceinline__ void wave_lds_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// ---------------------------------------------------------------------------
+// Trilinear interpolation.  (gx,gy,gz) are grid coordinates ((p - origin)/h);
+// each is clamped to [0, n-1], the cell corner is min(floor, n-2).  toff is the
+// byte offset of the atom type's block.
+struct Tri {
+    __amdgpu_buffer_rsrc_t rs;
+    uint32_t row, slab;
+    float mx, my, mz, m2x, m2y, m2z, fnx, fslab;
+};
+
+__device__ __forceinline__ Tri make_tri(const GridArgs &g) {
+    Tri t;
+    t.rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.values, (short)0, (int)g.bytes, 0x00020000);
+    t.row = g.row_bytes;
+    t.slab = g.slab_bytes;
+    t.mx = g.mx; t.my = g.my; t.mz = g.mz;
+    t.m2x = g.m2x; t.m2y = g.m2y; t.m2z = g.m2z;
+    t.fnx = g.fnx; t.fslab = g.fslab;
+    return t;
+}
+
+// cell offset (bytes within the type block) and fractions
+__device__ __forceinline__ uint32_t tri_cell(const Tri &t, float gx, float gy, float gz, float &fx,
+                                             float &fy, float &fz) {
+    const float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
+    const float cy = __builtin_amdgcn_fmed3f(gy, 0.0f, t.my);
+    const float cz = __builtin_amdgcn_fmed3f(gz, 0.0f, t.mz);
+    const float ix = floorf(__builtin_amdgcn_fmed3f(gx, 0.0f, t.m2x));
+    const float iy = floorf(__builtin_amdgcn_fmed3f(gy, 0.0f, t.m2y));
+    const float iz = floorf(__builtin_amdgcn_fmed3f(gz, 0.0f, t.m2z));
+    fx = cx - ix;
+    fy = cy - iy;
+    fz = cz - iz;
+    // element index < 2^24: exact in float
+    const float e = fmaf(iz, t.fslab, fmaf(iy, t.fnx, ix));
+    return ((uint32_t)e) << 2;
+}
+
+__device__ __forceinline__ float tri_blend(float v000, float v100, float v010, float v110,
+                                           float v001, float v101, float v011, float v111,
+                                           float fx, float fy, float fz) {
+    const float c00 = fmaf(fx, v100 - v000, v000);
+    const float c10 = fmaf(fx, v110 - v010, v010);
+    const float c01 = fmaf(fx, v101 - v001, v001);
+    const float c11 = fmaf(fx, v111 - v011, v011);
+    const float c0 = fmaf(fy, c10 - c00, c00);
+    const float c1 = fmaf(fy, c11 - c01, c01);
+    return fmaf(fz, c1 - c0, c0);
+}
+
+// 32-bit raw buffer load; the builtin returns the bits as an integer.
+__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, int soff) {
+    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, soff, 0));
+}
+
+// wave-uniform type offset (scalar offsets for the 8 corners)
+__device__ __forceinline__ float tri_u(const Tri &t, float gx, float gy, float gz, int toff) {
+    float fx, fy, fz;
+    const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz);
+    const int r = (int)t.row, s = (int)t.slab;
+    const float v000 = ld(t.rs, off, toff);
+    const float v100 = ld(t.rs, off, toff + 4);
+    const float v010 = ld(t.rs, off, toff + r);
+    const float v110 = ld(t.rs, off, toff + r + 4);
+    const float v001 = ld(t.rs, off, toff + s);
+    const float v101 = ld(t.rs, off, toff + s + 4);
+    const float v011 = ld(t.rs, off, toff + s + r);
+    const float v111 = ld(t.rs, off, toff + s + r + 4);
+    return tri_blend(v000, v100, v010, v110, v001, v101, v011, v111, fx, fy, fz);
+}
+
+// per-lane type offset
+__device__ __forceinline__ float tri_v(const Tri &t, float gx, float gy, float gz, uint32_t toff) {
+    float fx, fy, fz;
+    const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz) + toff;
+    const int r = (int)t.row, s = (int)t.slab;
+    const float v000 = ld(t.rs, off, 0);
+    const float v100 = ld(t.rs, off, 4);
+    const float v010 = ld(t.rs, off, r);
+    const float v110 = ld(t.rs, off, r + 4);
+    const float v001 = ld(t.rs, off, s);
+    const float v101 = ld(t.rs, off, s + 4);
+    const float v011 = ld(t.rs, off, s + r);
+    const float v111 = ld(t.rs, off, s + r + 4);
+    return tri_blend(v000, v100, v010, v110, v001, v101, v011, v111, fx, fy, fz);
+}
+
+// ---------------------------------------------------------------------------
+// Pose held across lanes: atom i = lane + 64*s in slot s.
+template <int NS>
+struct Pose {
+    float x[NS], y[NS], z[NS];
+};
+
+template <int NS>
+__device__ __forceinline__ void pick_atom(const Pose<NS> &Y, int i, float &px, float &py,
+                                          float &pz) {
+    const int l = i & 63, s = i >> 6;
+    px = read_lane(Y.x[0], l);
+    py = read_lane(Y.y[0], l);
+    pz = read_lane(Y.z[0], l);
+#pragma unroll
+    for (int q = 1; q < NS; ++q) {
+        if (s == q) {
+            px = read_lane(Y.x[q], l);
+            py = read_lane(Y.y[q], l);
+            pz = read_lane(Y.z[q], l);
+        }
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ void centroid(const Pose<NS> &Y, int n, float &cx, float &cy,
+                                         float &cz) {
+    float sx = 0.f, sy = 0.f, sz = 0.f;
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        if (lane + 64 * s < n) {
+            sx += Y.x[s];
+            sy += Y.y[s];
+            sz += Y.z[s];
+        }
+    }
+    const float inv = 1.0f / (float)n;
+    cx = wave_sum(sx) * inv;
+    cy = wave_sum(sy) * inv;
+    cz = wave_sum(sz) * inv;
+}
+
+// Generate_Starting_Pose: Y = S_r (X - c0) + grid centre.  X rows in LDS (x,y,z,toff).
+template <int NS>
+__device__ __forceinline__ void start_pose(Pose<NS> &Y, const float4 *xyzt, int n, int r,
+                                           const GridArgs &g, const SearchArgs &sa) {
+    const int lane = lane_id();
+    Pose<NS> X;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = lane + 64 * s;
+        const float4 v = i < n ? xyzt[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+        X.x[s] = v.x;
+        X.y[s] = v.y;
+        X.z[s] = v.z;
+    }
+    float c0x, c0y, c0z;
+    centroid(X, n, c0x, c0y, c0z);
+    const float4 m0 = sa.smat[3 * r + 0], m1 = sa.smat[3 * r + 1], m2 = sa.smat[3 * r + 2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const float dx = X.x[s] - c0x, dy = X.y[s] - c0y, dz = X.z[s] - c0z;
+        Y.x[s] = fmaf(m0.x, dx, fmaf(m0.y, dy, fmaf(m0.z, dz, g.cx)));
+        Y.y[s] = fmaf(m1.x, dx, fmaf(m1.y, dy, fmaf(m1.z, dz, g.cy)));
+        Y.z[s] = fmaf(m2.x, dx, fmaf(m2.y, dy, fmaf(m2.z, dz, g.cz)));
+    }
+}
+
+// Apply alignment orientation o about the pose centroid.
+template <int NS>
+__device__ __forceinline__ void apply_align(Pose<NS> &Y, int n, int o, const SearchArgs &sa) {
+    float cx, cy, cz;
+    centroid(Y, n, cx, cy, cz);
+    const float4 m0 = sa.amat[3 * o + 0], m1 = sa.amat[3 * o + 1], m2 = sa.amat[3 * o + 2];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const float dx = Y.x[s] - cx, dy = Y.y[s] - cy, dz = Y.z[s] - cz;
+        Y.x[s] = fmaf(m0.x, dx, fmaf(m0.y, dy, fmaf(m0.z, dz, cx)));
+        Y.y[s] = fmaf(m1.x, dx, fmaf(m1.y, dy, fmaf(m1.z, dz, cy)));
+        Y.z[s] = fmaf(m2.x, dx, fmaf(m2.y, dy, fmaf(m2.z, dz, cz)));
+    }
+}
+
+// Alignment (Rigid Rotation): lanes over the A*A orientations, loop over atoms.
+// rec: per-wave LDS, >= n float4.  toff[s]: type byte offset of this lane's atoms.
+// Applies and returns the best orientation; *best_out = its score.
+template <int NS>
+__device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec, const Tri &tr,
+                          const GridArgs &g, const SearchArgs &sa, float *best_out) {
+    const int lane = lane_id();
+    float cx, cy, cz;
+    centroid(Y, n, cx, cy, cz);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = lane + 64 * s;
+        if (i < n)
+            rec[i] = make_float4((Y.x[s] - cx) * g.inv_h, (Y.y[s] - cy) * g.inv_h,
+                                 (Y.z[s] - cz) * g.inv_h, __int_as_float(toff[s]));
+    }
+    wave_lds_sync();
+    const float ex = (cx - g.ox) * g.inv_h, ey = (cy - g.oy) * g.inv_h, ez = (cz - g.oz) * g.inv_h;
+    const int NO = sa.A * sa.A;
+    u64 best = 0;
+    for (int base = 0; base < NO; base += 64) {
+        const int o = base + lane;
+        const bool ov = o < NO;
+        const int oo = ov ? o : 0;
+        const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1], m2 = sa.amat[3 * oo + 2];
+        float acc = 0.f;
+        for (int a = 0; a < n; ++a) {
+            const float4 r = rec[a];
+            const int to = uniform_int(__float_as_int(r.w));
+            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
+            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
+            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
+            acc += tri_u(tr, gx, gy, gz, to);
+        }
+        const u64 key = ov ? make_key(acc, (uint32_t)o) : 0ull;
+        best = key > best ? key : best;
+    }
+    best = wave_max_u64(best);
+    const int ob = (int)key_index(best);
+    if (best_out) *best_out = key_score(best);
+    wave_lds_sync();  // rec is rewritten by the caller next
+    apply_align(Y, n, ob, sa);
+    return ob;
+}
+
+// Rotation frame of bond (a,b) for this lane's atoms: p = a + u(u.v),
+// vp = v - u(u.v), w = u x v, with v = Y_i - a; a rotation by theta sends Y_i to
+// p + cos(theta) vp + sin(theta) w.
+struct Axis {
+    float ax, ay, az, ux, uy, uz;
+};
+
+template <int NS>
+__device__ __forceinline__ Axis bond_axis(const Pose<NS> &Y, int a, int b) {
+    Axis A;
+    float bx, by, bz;
+    pick_atom(Y, a, A.ax, A.ay, A.az);
+    pick_atom(Y, b, bx, by, bz);
+    const float dx = bx - A.ax, dy = by - A.ay, dz = bz - A.az;
+    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    A.ux = dx * inv;
+    A.uy = dy * inv;
+    A.uz = dz * inv;
+    return A;
+}
+
+__device__ __forceinline__ void torsion_frame(const Axis &A, float x, float y, float z, float &px,
+                                              float &py, float &pz, float &vx, float &vy,
+                                              float &vz, float &wx, float &wy, float &wz) {
+    const float dx = x - A.ax, dy = y - A.ay, dz = z - A.az;
+    const float ud = A.ux * dx + A.uy * dy + A.uz * dz;
+    px = fmaf(A.ux, ud, A.ax);
+    py = fmaf(A.uy, ud, A.ay);
+    pz = fmaf(A.uz, ud, A.az);
+    vx = fmaf(-A.ux, ud, dx);
+    vy = fmaf(-A.uy, ud, dy);
+    vz = fmaf(-A.uz, ud, dz);
+    wx = A.uy * dz - A.uz * dy;
+    wy = A.uz * dx - A.ux * dz;
+    wz = A.ux * dy - A.uy * dx;
+}
+
+template <int NS>
+__device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, int a, int b, float c,
+                                              float sn) {
+    const int lane = lane_id();
+    const Axis A = bond_axis(Y, a, b);
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const bool mv = (mrow[s] >> lane) & 1ull;
+        if (mv) {
+            float px, py, pz, vx, vy, vz, wx, wy, wz;
+            torsion_frame(A, Y.x[s], Y.y[s], Y.z[s], px, py, pz, vx, vy, vz, wx, wy, wz);
+            Y.x[s] = fmaf(sn, wx, fmaf(c, vx, px));
+            Y.y[s] = fmaf(sn, wy, fmaf(c, vy, py));
+            Y.z[s] = fmaf(sn, wz, fmaf(c, vz, pz));
+        }
+    }
+}
+
+// One torsion decision (Optimize Pose, inner angle loop) for rotatable bond with
+// moving-mask row mrow (NS words), axis atoms (a,b).  cs[c] = (cos,sin) of this
+// lane's candidates k = lane + 64c.  Returns the applied step or kTraceNone.
+template <int NS, int C>
+__device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
+                              const u64 *far, const int (&toff)[NS], float4 *rec,
+                              const float2 (&cs)[C], const Tri &tr, const GridArgs &g,
+                              const SearchArgs &sa) {
+    const int lane = lane_id();
+    const Axis A = bond_axis(Y, a, b);
+    u64 mw[NS];
+    int m = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        mw[s] = mrow[s];
+        m += __popcll(mw[s]);
+    }
+    // moving-atom frames -> LDS (grid units), static atoms -> registers
+    float sgx[NS], sgy[NS], sgz[NS];
+    bool st[NS];
+    int before = 0;
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = lane + 64 * s;
+        const bool mv = (mw[s] >> lane) & 1ull;
+        st[s] = !mv && i < n;
+        sgx[s] = (Y.x[s] - g.ox) * g.inv_h;
+        sgy[s] = (Y.y[s] - g.oy) * g.inv_h;
+        sgz[s] = (Y.z[s] - g.oz) * g.inv_h;
+        if (mv) {
+            float px, py, pz, vx, vy, vz, wx, wy, wz;
+            torsion_frame(A, Y.x[s], Y.y[s], Y.z[s], px, py, pz, vx, vy, vz, wx, wy, wz);
+            const int q = before + (int)__builtin_amdgcn_mbcnt_hi(
+                                       (uint32_t)(mw[s] >> 32),
+                                       __builtin_amdgcn_mbcnt_lo((uint32_t)mw[s], 0u));
+            rec[3 * q + 0] = make_float4((px - g.ox) * g.inv_h, (py - g.oy) * g.inv_h,
+                                         (pz - g.oz) * g.inv_h, __int_as_float(toff[s]));
+            rec[3 * q + 1] = make_float4(vx * g.inv_h, vy * g.inv_h, vz * g.inv_h,
+                                         __int_as_float(i));
+            rec[3 * q + 2] = make_float4(wx * g.inv_h, wy * g.inv_h, wz * g.inv_h, 0.f);
+        }
+        before += __popcll(mw[s]);
+    }
+    wave_lds_sync();
+
+    // score every candidate on the moving fragment
+    float acc[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) acc[c] = 0.f;
+    for (int q = 0; q < m; ++q) {
+        const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
+        const int to = uniform_int(__float_as_int(r0.w));
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float gx = fmaf(cs[c].y, r2.x, fmaf(cs[c].x, r1.x, r0.x));
+            const float gy = fmaf(cs[c].y, r2.y, fmaf(cs[c].x, r1.y, r0.y));
+            const float gz = fmaf(cs[c].y, r2.z, fmaf(cs[c].x, r1.z, r0.z));
+            acc[c] += tri_u(tr, gx, gy, gz, to);
+        }
+    }
+    u64 key[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = lane + 64 * c;
+        key[c] = k < sa.T ? make_key(acc[c], (uint32_t)k) : 0ull;
+    }
+
+    // best-first bump check
+    int kstar = kTraceNone;
+    for (;;) {
+        u64 best = key[0];
+#pragma unroll
+        for (int c = 1; c < C; ++c) best = key[c] > best ? key[c] : best;
+        best = wave_max_u64(best);
+        if (best == 0ull) break;
+        const int k = (int)key_index(best);
+        const float2 t = sa.tors[k];
+        bool bump = false;
+        for (int q = 0; q < m; ++q) {
+            const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
+            const int i = uniform_int(__float_as_int(r1.w));
+            const float zx = fmaf(t.y, r2.x, fmaf(t.x, r1.x, r0.x));
+            const float zy = fmaf(t.y, r2.y, fmaf(t.x, r1.y, r0.y));
+            const float zz = fmaf(t.y, r2.z, fmaf(t.x, r1.z, r0.z));
+            bool hit = false;
+#pragma unroll
+            for (int s = 0; s < NS; ++s) {
+                const u64 fw = far[i * NS + s];
+                const bool el = st[s] && ((fw >> lane) & 1ull);
+                const float dx = zx - sgx[s], dy = zy - sgy[s], dz = zz - sgz[s];
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                hit = hit || (el && d2 < sa.bump2g);
+            }
+            if (__ballot(hit) != 0ull) {
+                bump = true;
+                break;
+            }
+        }
+        if (!bump) {
+            kstar = k;
+            break;
+        }
+#pragma unroll
+        for (int c = 0; c < C; ++c)
+            if (c == (k >> 6) && lane == (k & 63)) key[c] = 0ull;
+    }
+    wave_lds_sync();  // rec is rewritten next
+    if (kstar != (int)kTraceNone) {
+        const float2 t = sa.tors[kstar];
+        apply_torsion(Y, mrow, a, b, t.x, t.y);
+    }
+    return kstar;
+}
+
+// Score of the pose: sum over atoms of the grid of the atom's type.
+template <int NS>
+__device__ __forceinline__ float pose_score(const Pose<NS> &Y, int n, const int (&toff)[NS],
+                                            const Tri &tr, const GridArgs &g) {
+    const int lane = lane_id();
+    float s = 0.f;
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        if (lane + 64 * q < n)
+            s += tri_v(tr, (Y.x[q] - g.ox) * g.inv_h, (Y.y[q] - g.oy) * g.inv_h,
+                       (Y.z[q] - g.oz) * g.inv_h, (uint32_t)toff[q]);
+    }
+    return wave_sum(s);
+}
+
+// ---------------------------------------------------------------------------
+// Shared-memory layout (bytes), identical for host and device.
+struct Lds {
+    static __host__ __device__ size_t xyzt(int nmax) { return 0; }
+    static __host__ __device__ size_t far(int nmax) { return (size_t)nmax * 16; }
+    static __host__ __device__ size_t mask(int nmax, int nw) {
+        return far(nmax) + (size_t)nmax * nw * 8;
+    }
+    static __host__ __device__ size_t rot(int nmax, int nw) {
+        return mask(nmax, nw) + (size_t)kMaxRot * nw * 8;
+    }
+    static __host__ __device__ size_t misc(int nmax, int nw) {
+        return rot(nmax, nw) + (size_t)kMaxRot * 8;
+    }
+    static __host__ __device__ size_t rec(int nmax, int nw) { return misc(nmax, nw) + 16; }
+    static __host__ __device__ size_t rec_stride(int nmax) { return (size_t)nmax * 48; }
+};
+
+static inline __host__ __device__ int bin_nmax(int bin) { return 32 * (bin + 1); }
+static inline __host__ __device__ int bin_slots(int bin) { return (bin_nmax(bin) + 63) / 64; }
+
+size_t dock_lds_bytes(int nmax, int waves) {
+    const int nw = (nmax + 63) / 64;
+    return Lds::rec(nmax, nw) + (size_t)waves * Lds::rec_stride(nmax);
+}
+
+// Stage ligand l into LDS (whole workgroup).
+template <int NS>
+__device__ void stage_ligand(unsigned char *smem, int nmax, int l, const LibArgs &lib,
+                             const WorkArgs &ws, const GridArgs &g, bool with_far) {
+    float4 *xyzt = (float4 *)(smem + Lds::xyzt(nmax));
+    u64 *far = (u64 *)(smem + Lds::far(nmax));
+    u64 *mask = (u64 *)(smem + Lds::mask(nmax, NS));
+    int2 *rot = (int2 *)(smem + Lds::rot(nmax, NS));
+    int *misc = (int *)(smem + Lds::misc(nmax, NS));
+    const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+    const int r0 = lib.rot_off[l], B = lib.rot_off[l + 1] - r0;
+    for (int i = threadIdx.x; i < n; i += blockDim.x) {
+        const float *p = lib.xyz + 3 * (size_t)(a0 + i);
+        const int toff = (int)lib.type[a0 + i] * (int)g.type_bytes;
+        xyzt[i] = make_float4(p[0], p[1], p[2], __int_as_float(toff));
+    }
+    if (with_far) {
+        for (int e = threadIdx.x; e < n * NS; e += blockDim.x) {
+            const int i = e / NS, w = e - i * NS;
+            far[e] = ws.far[(size_t)(a0 + i) * kFarWords + w];
+        }
+    }
+    for (int e = threadIdx.x; e < B * NS; e += blockDim.x) {
+        const int b = e / NS, w = e - b * NS;
+        mask[e] = w < lib.mask_words ? lib.rot_mask[(size_t)(r0 + b) * lib.mask_words + w] : 0ull;
+    }
+    for (int b = threadIdx.x; b < B; b += blockDim.x)
+        rot[b] = make_int2(lib.rot_bond[2 * (size_t)(r0 + b)], lib.rot_bond[2 * (size_t)(r0 + b) + 1]);
+    if (threadIdx.x == 0) {
+        misc[1] = n;
+        misc[2] = B;
+    }
+}
+
+template <int NS>
+__device__ __forceinline__ void lane_toff(const float4 *xyzt, int n, int (&toff)[NS]) {
+    const int lane = lane_id();
+#pragma unroll
+    for (int s = 0; s < NS; ++s) {
+        const int i = lane + 64 * s;
+        toff[s] = i < n ? __float_as_int(xyzt[i].w) : 0;
+    }
+}
+
+static __device__ __forceinline__ size_t trace_base(const LibArgs &lib, const SearchArgs &sa, int l) {
+    return (size_t)sa.R * ((size_t)l + (size_t)sa.P * (size_t)lib.rot_off[l]);
+}
+
+// ---------------------------------------------------------------------------
+// Docking kernel: persistent workgroups pop (ligand, restart-group) items of one
+// size bin; each wave docks one restart.
+template <int NS, int C>
+__global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
+                                              int bin) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nmax = bin_nmax(bin);
+    const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
+    float4 *xyzt = (float4 *)(smem + Lds::xyzt(nmax));
+    const u64 *far = (const u64 *)(smem + Lds::far(nmax));
+    const u64 *mask = (const u64 *)(smem + Lds::mask(nmax, NS));
+    const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
+    int *misc = (int *)(smem + Lds::misc(nmax, NS));
+    float4 *rec = (float4 *)(smem + Lds::rec(nmax, NS) + (size_t)wave * Lds::rec_stride(nmax));
+    const Tri tr = make_tri(g);
+
+    float2 cs[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = lane + 64 * c;
+        cs[c] = k < sa.T ? sa.tors[k] : make_float2(1.f, 0.f);
+    }
+    const int groups = (sa.R + W - 1) / W;
+    const long long total = (long long)ws.counters[bin] * groups;
+    int cur = -1;
+    for (;;) {
+        if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[kNumBins + bin], 1);
+        __syncthreads();
+        const int item = misc[0];
+        if ((long long)item >= total) break;
+        const int li = item / groups, grp = item - li * groups;
+        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        if (l != cur) {
+            stage_ligand<NS>(smem, nmax, l, lib, ws, g, true);
+            cur = l;
+        }
+        __syncthreads();
+        const int r = grp * W + wave;
+        if (r < sa.R) {
+            const int n = misc[1], B = misc[2];
+            int toff[NS];
+            lane_toff(xyzt, n, toff);
+            Pose<NS> Y;
+            start_pose(Y, xyzt, n, r, g, sa);
+            uint16_t *tr_out = ws.rtrace + trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B);
+            const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr);
+            if (lane == 0) tr_out[0] = (uint16_t)o;
+            int d = 1;
+            for (int p = 0; p < sa.P; ++p) {
+                for (int b = 0; b < B; ++b, ++d) {
+                    const int2 ab = rot[b];
+                    const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
+                                                        uniform_int(ab.y), far, toff, rec, cs, tr,
+                                                        g, sa);
+                    if (lane == 0) tr_out[d] = (uint16_t)k;
+                }
+            }
+            const float sc = pose_score(Y, n, toff, tr, g);
+            if (lane == 0) ws.rscore[(size_t)l * sa.R + r] = sc;
+        }
+        __syncthreads();
+    }
+}
+
+// Replay restart r of ligand l from its decision trace (same arithmetic as k_dock).
+template <int NS>
+__device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, const int2 *rot,
+                            int n, int B, int r, const uint16_t *trace, const GridArgs &g,
+                            const SearchArgs &sa) {
+    start_pose(Y, xyzt, n, r, g, sa);
+    const int o = (int)trace[0];
+    apply_align(Y, n, o < sa.A * sa.A ? o : 0, sa);  // indices come from k_dock; bound anyway
+    int d = 1;
+    for (int p = 0; p < sa.P; ++p)
+        for (int b = 0; b < B; ++b, ++d) {
+            const int k = trace[d];
+            if (k < sa.T) {
+                const float2 t = sa.tors[k];
+                const int2 ab = rot[b];
+                apply_torsion(Y, mask + b * NS, uniform_int(ab.x), uniform_int(ab.y), t.x, t.y);
+            }
+        }
+}
+
+// ---------------------------------------------------------------------------
+// Select Poses + final rigid step + output, one workgroup per ligand (persistent
+// over the bin list).
+size_t final_lds_bytes(int nmax, int waves, int R, int K) {
+    const int nw = (nmax + 63) / 64;
+    return Lds::rec(nmax, nw) + (size_t)waves * (size_t)nmax * 16 + (size_t)R * 12 +
+           (size_t)K * 16 + 64;
+}
+
+template <int NS>
+__global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
+                                               WorkArgs ws, OutArgs out, int bin) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nmax = bin_nmax(bin);
+    const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
+    const int R = sa.R, K = sa.K;
+    float4 *xyzt = (float4 *)(smem + Lds::xyzt(nmax));
+    const u64 *mask = (const u64 *)(smem + Lds::mask(nmax, NS));
+    const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
+    int *misc = (int *)(smem + Lds::misc(nmax, NS));
+    unsigned char *p = smem + Lds::rec(nmax, NS);
+    float4 *rec = (float4 *)(p + (size_t)wave * nmax * 16);
+    p += (size_t)W * nmax * 16;
+    u64 *rkey = (u64 *)p;                 // [R]
+    int *order = (int *)(p + (size_t)R * 8);  // [R]
+    int *sel = (int *)(p + (size_t)R * 12);   // [K]
+    float *fsc = (float *)(sel + K);          // [K]
+    int *fo = (int *)(fsc + K);               // [K]
+    int *rank = fo + K;                       // [K]
+    int *nsel = rank + K;                     // [1]
+    const Tri tr = make_tri(g);
+
+    for (;;) {
+        if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[2 * kNumBins + bin], 1);
+        __syncthreads();
+        const int li = misc[0];
+        if (li >= ws.counters[bin]) break;
+        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        stage_ligand<NS>(smem, nmax, l, lib, ws, g, false);
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            const float s = ws.rscore[(size_t)l * R + r];
+            rkey[r] = make_key(s, (uint32_t)r);
+            if (out.rscore_user) out.rscore_user[(size_t)l * R + r] = s;
+        }
+        __syncthreads();
+        // order restarts by (score desc, restart asc): rank = number of larger keys
+        for (int r = threadIdx.x; r < R; r += blockDim.x) {
+            const u64 kr = rkey[r];
+            int rk = 0;
+            for (int q = 0; q < R; ++q) rk += rkey[q] > kr;
+            order[rk] = r;
+        }
+        __syncthreads();
+        const int n = misc[1], B = misc[2];
+        const int a0 = lib.atom_off[l];
+        float *accp = ws.acc_pose + (size_t)a0 * K * 3;
+        const uint16_t *trl = ws.rtrace + trace_base(lib, sa, l);
+        const int D = 1 + sa.P * B;
+        if (wave == 0) {
+            // greedy selection with plain-RMSD dedup; poses rebuilt from traces
+            int ns = 0;
+            const float lim = sa.dedup2 * (float)n;
+            for (int t = 0; t < R && ns < K; ++t) {
+                const int r = order[t];
+                Pose<NS> Y;
+                replay_pose(Y, xyzt, mask, rot, n, B, r, trl + (size_t)r * D, g, sa);
+                bool keep = true;
+                if (sa.dedup2 > 0.f) {
+                    for (int s = 0; s < ns && keep; ++s) {
+                        float ssd = 0.f;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) {
+                            const int i = lane + 64 * q;
+                            if (i < n) {
+                                const float *P = accp + ((size_t)s * n + i) * 3;
+                                const float dx = Y.x[q] - P[0], dy = Y.y[q] - P[1],
+                                            dz = Y.z[q] - P[2];
+                                ssd += dx * dx + dy * dy + dz * dz;
+                            }
+                        }
+                        ssd = wave_sum(ssd);
+                        if (ssd < lim) keep = false;
+                    }
+                }
+                if (keep) {
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        const int i = lane + 64 * q;
+                        if (i < n) {
+                            float *P = accp + ((size_t)ns * n + i) * 3;
+                            P[0] = Y.x[q];
+                            P[1] = Y.y[q];
+                            P[2] = Y.z[q];
+                        }
+                    }
+                    if (lane == 0) sel[ns] = r;
+                    ++ns;
+                }
+            }
+            if (lane == 0) *nsel = ns;
+        }
+        __syncthreads();
+        const int ns = *nsel;
+        int toff[NS];
+        lane_toff(xyzt, n, toff);
+        // final rigid step on each kept pose
+        for (int s = wave; s < ns; s += W) {
+            Pose<NS> Y;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q;
+                const float *P = accp + ((size_t)s * n + (i < n ? i : 0)) * 3;
+                Y.x[q] = P[0];
+                Y.y[q] = P[1];
+                Y.z[q] = P[2];
+            }
+            int o = 0;
+            if (sa.final_align) o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr);
+            const float sc = pose_score(Y, n, toff, tr, g);
+            if (lane == 0) {
+                fsc[s] = sc;
+                fo[s] = o;
+            }
+        }
+        __syncthreads();
+        // output order: final score desc, restart asc
+        for (int s = threadIdx.x; s < ns; s += blockDim.x) {
+            const u64 ks = make_key(fsc[s], (uint32_t)sel[s]);
+            int rk = 0;
+            for (int q = 0; q < ns; ++q) rk += make_key(fsc[q], (uint32_t)sel[q]) > ks;
+            rank[s] = rk;
+        }
+        __syncthreads();
+        for (int s = wave; s < ns; s += W) {
+            Pose<NS> Y;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q;
+                const float *P = accp + ((size_t)s * n + (i < n ? i : 0)) * 3;
+                Y.x[q] = P[0];
+                Y.y[q] = P[1];
+                Y.z[q] = P[2];
+            }
+            if (sa.final_align) apply_align(Y, n, fo[s], sa);
+            const int rk = rank[s];
+            float *O = out.pxyz + ((size_t)a0 * K + (size_t)rk * n) * 3;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n) {
+                    O[3 * i + 0] = Y.x[q];
+                    O[3 * i + 1] = Y.y[q];
+                    O[3 * i + 2] = Y.z[q];
+                }
+            }
+            if (lane == 0) {
+                out.pscore[(size_t)l * K + rk] = fsc[s];
+                out.prestart[(size_t)l * K + rk] = sel[s];
+                if (out.ftrace) out.ftrace[(size_t)l * K + rk] = (uint16_t)fo[s];
+                if (rk == 0) out.best[l] = fsc[s];
+            }
+        }
+        for (int e = threadIdx.x; e < (K - ns) * n * 3; e += blockDim.x)
+            out.pxyz[((size_t)a0 * K + (size_t)ns * n) * 3 + e] = 0.f;
+        for (int s = ns + (int)threadIdx.x; s < K; s += blockDim.x) {
+            out.pscore[(size_t)l * K + s] = -INFINITY;
+            out.prestart[(size_t)l * K + s] = -1;
+            if (out.ftrace) out.ftrace[(size_t)l * K + s] = 0;
+        }
+        if (threadIdx.x == 0) {
+            out.npose[l] = ns;
+            if (ns == 0) out.best[l] = -INFINITY;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Preparation: one wavefront per ligand.  Checks the ligand, builds its
+// bump-pair rows (pairs at least bmin bonds apart), and appends it to its size
+// bin.  A ligand that fails a check gets a status and empty outputs.
+__global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
+                                             OutArgs out) {
+    __shared__ u64 adj[kMaxAtoms * 4];   // adjacency + self rows
+    const int l = blockIdx.x;
+    const int lane = lane_id();
+    if (l >= lib.L) return;
+    int status = 0;
+    const int a0 = lib.atom_off[l], a1 = lib.atom_off[l + 1];
+    const int b0 = lib.bond_off[l], b1 = lib.bond_off[l + 1];
+    const int r0 = lib.rot_off[l], r1 = lib.rot_off[l + 1];
+    const int n = a1 - a0, nb = b1 - b0, B = r1 - r0;
+    if (a0 < 0 || a1 < a0 || (long long)a1 > lib.A_total || b0 < 0 || b1 < b0 ||
+        (long long)b1 > lib.Nb_total || r0 < 0 || r1 < r0 || (long long)r1 > lib.Nr_total)
+        status = 5;
+    else if (n < 1 || n > kMaxAtoms || B > kMaxRot || nb > 8 * n || n > 64 * lib.mask_words)
+        status = 1;
+    const int NW = (n + 63) >> 6;
+    if (status == 0) {
+        bool bad = false;
+        for (int i = lane; i < n; i += 64) bad |= (int)lib.type[a0 + i] >= g.ntypes;
+        if (__ballot(bad)) status = 2;
+    }
+    if (status == 0) {
+        for (int e = lane; e < 4 * n; e += 64) adj[e] = 0ull;
+        __syncthreads();
+        for (int i = lane; i < n; i += 64) atomicOr(&adj[i * 4 + (i >> 6)], 1ull << (i & 63));
+        bool bad = false;
+        for (int e = lane; e < nb; e += 64) {
+            const int u = lib.bond[2 * (size_t)(b0 + e)], v = lib.bond[2 * (size_t)(b0 + e) + 1];
+            if (u < 0 || v < 0 || u >= n || v >= n || u == v) {
+                bad = true;
+            } else {
+                atomicOr(&adj[u * 4 + (v >> 6)], 1ull << (v & 63));
+                atomicOr(&adj[v * 4 + (u >> 6)], 1ull << (u & 63));
+            }
+        }
+        for (int e = lane; e < B; e += 64) {
+            const int a = lib.rot_bond[2 * (size_t)(r0 + e)], b = lib.rot_bond[2 * (size_t)(r0 + e) + 1];
+            if (a < 0 || b < 0 || a >= n || b >= n || a == b) bad = true;
+        }
+        if (__ballot(bad)) status = 3;
+        __syncthreads();
+    }
+    if (status == 0) {
+        // every rotatable bond is a bond
+        bool bad = false;
+        for (int e = lane; e < B; e += 64) {
+            const int a = lib.rot_bond[2 * (size_t)(r0 + e)], b = lib.rot_bond[2 * (size_t)(r0 + e) + 1];
+            bad |= !((adj[a * 4 + (b >> 6)] >> (b & 63)) & 1ull);
+        }
+        if (__ballot(bad)) status = 3;
+    }
+    if (status == 0) {
+        // connected: closure of {0} under adjacency
+        u64 reach[4] = {1ull, 0ull, 0ull, 0ull};
+        for (int it = 0; it < n; ++it) {
+            u64 nr[4] = {0ull, 0ull, 0ull, 0ull};
+            for (int i = lane; i < n; i += 64)
+                if ((reach[i >> 6] >> (i & 63)) & 1ull)
+                    for (int w = 0; w < NW; ++w) nr[w] |= adj[i * 4 + w];
+            bool changed = false;
+            for (int w = 0; w < NW; ++w) {
+                nr[w] = wave_or_u64(nr[w]) | reach[w];
+                changed |= nr[w] != reach[w];
+                reach[w] = nr[w];
+            }
+            if (!changed) break;
+        }
+        int cnt = 0;
+        for (int w = 0; w < NW; ++w) cnt += __popcll(reach[w]);
+        if (cnt != n) status = 4;
+    }
+    if (status == 0) {
+        // each mask: contains b, not a, no bit >= n, and no bond other than a-b crosses it
+        bool bad = false;
+        for (int rb = 0; rb < B && !bad; ++rb) {
+            const int a = lib.rot_bond[2 * (size_t)(r0 + rb)], b = lib.rot_bond[2 * (size_t)(r0 + rb) + 1];
+            u64 m[4] = {0ull, 0ull, 0ull, 0ull};
+            for (int w = 0; w < lib.mask_words && w < 4; ++w)
+                m[w] = lib.rot_mask[(size_t)(r0 + rb) * lib.mask_words + w];
+            for (int w = NW; w < lib.mask_words; ++w)
+                if (lib.rot_mask[(size_t)(r0 + rb) * lib.mask_words + w] != 0ull) bad = true;
+            if ((n & 63) != 0 && (m[NW - 1] >> (n & 63)) != 0ull) bad = true;
+            if (!((m[b >> 6] >> (b & 63)) & 1ull) || ((m[a >> 6] >> (a & 63)) & 1ull)) bad = true;
+            bool cross = false;
+            for (int e = lane; e < nb; e += 64) {
+                const int u = lib.bond[2 * (size_t)(b0 + e)], v = lib.bond[2 * (size_t)(b0 + e) + 1];
+                if ((u == a && v == b) || (u == b && v == a)) continue;
+                const bool su = (m[u >> 6] >> (u & 63)) & 1ull, sv = (m[v >> 6] >> (v & 63)) & 1ull;
+                cross |= su != sv;
+            }
+            if (__ballot(cross)) bad = true;
+        }
+        if (bad) status = 4;
+    }
+    if (status == 0) {
+        // rows of atoms within bmin-1 bonds, complemented: the bump-checked pairs
+        for (int i = lane; i < n; i += 64) {
+            u64 near[4] = {0ull, 0ull, 0ull, 0ull};
+            near[i >> 6] = 1ull << (i & 63);
+            for (int step = 1; step < sa.bmin; ++step) {
+                u64 nx[4] = {near[0], near[1], near[2], near[3]};
+                for (int w = 0; w < NW; ++w) {
+                    u64 bits = near[w];
+                    while (bits) {
+                        const int j = 64 * w + __ffsll((long long)bits) - 1;
+                        bits &= bits - 1;
+                        for (int v = 0; v < NW; ++v) nx[v] |= adj[j * 4 + v];
+                    }
+                }
+                for (int w = 0; w < 4; ++w) near[w] = nx[w];
+            }
+            for (int w = 0; w < kFarWords; ++w) {
+                u64 valid = 0ull;
+                if (w < NW) valid = (w == NW - 1 && (n & 63)) ? ((1ull << (n & 63)) - 1) : ~0ull;
+                ws.far[(size_t)(a0 + i) * kFarWords + w] = ~near[w] & valid;
+            }
+        }
+        if (lane == 0) {
+            const int bin = (n - 1) >> 5;
+            const int pos = atomicAdd(&ws.counters[bin], 1);
+            ws.bin_list[(size_t)bin * lib.L + pos] = l;
+        }
+    } else {
+        for (int s = lane; s < sa.K; s += 64) {
+            out.pscore[(size_t)l * sa.K + s] = -INFINITY;
+            out.prestart[(size_t)l * sa.K + s] = -1;
+            if (out.ftrace) out.ftrace[(size_t)l * sa.K + s] = 0;
+        }
+        if (lane == 0) {
+            out.best[l] = -INFINITY;
+            out.npose[l] = 0;
+        }
+    }
+    if (lane == 0) out.status[l] = status;
+}
+
+__global__ void k_reset(int *counters) {
+    if (threadIdx.x < 3 * kNumBins) counters[threadIdx.x] = 0;
+}
+
+// ---------------------------------------------------------------------------
+// launchers
+hipError_t launch_reset(int *counters, hipStream_t s) {
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters);
+    return hipGetLastError();
+}
+
+hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                       const WorkArgs &ws, const OutArgs &out, hipStream_t s) {
+    if (lib.L <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_prep, dim3(lib.L), dim3(64), 0, s, g, sa, lib, ws, out);
+    return hipGetLastError();
+}
+
+template <int NS, int C>
+static hipError_t launch_dock_t(int bin, int blocks, int waves, const GridArgs &g,
+                                const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                hipStream_t s) {
+    const size_t lds = dock_lds_bytes(bin_nmax(bin), waves);
+    hipFuncSetAttribute((const void *)k_dock<NS, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    hipLaunchKernelGGL((k_dock<NS, C>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, bin);
+    return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t launch_dock_c(int bin, int blocks, int waves, const GridArgs &g,
+                                const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                hipStream_t s) {
+    const int C = (sa.T + 63) / 64;
+    if (C <= 1) return launch_dock_t<NS, 1>(bin, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 2) return launch_dock_t<NS, 2>(bin, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 4) return launch_dock_t<NS, 4>(bin, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 8) return launch_dock_t<NS, 8>(bin, blocks, waves, g, sa, lib, ws, s);
+    return launch_dock_t<NS, 16>(bin, blocks, waves, g, sa, lib, ws, s);
+}
+
+hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                       const LibArgs &lib, const WorkArgs &ws, hipStream_t s) {
+    switch (bin_slots(bin)) {
+        case 1: return launch_dock_c<1>(bin, blocks, waves, g, sa, lib, ws, s);
+        case 2: return launch_dock_c<2>(bin, blocks, waves, g, sa, lib, ws, s);
+        case 3: return launch_dock_c<3>(bin, blocks, waves, g, sa, lib, ws, s);
+        default: return launch_dock_c<4>(bin, blocks, waves, g, sa, lib, ws, s);
+    }
+}
+
+template <int NS>
+static hipError_t launch_final_t(int bin, int blocks, int waves, const GridArgs &g,
+                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                 const OutArgs &out, hipStream_t s) {
+    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K);
+    hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    hipLaunchKernelGGL((k_final<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
+                       bin);
+    return hipGetLastError();
+}
+
+hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out,
+                        hipStream_t s) {
+    switch (bin_slots(bin)) {
+        case 1: return launch_final_t<1>(bin, blocks, waves, g, sa, lib, ws, out, s);
+        case 2: return launch_final_t<2>(bin, blocks, waves, g, sa, lib, ws, out, s);
+        case 3: return launch_final_t<3>(bin, blocks, waves, g, sa, lib, ws, out, s);
+        default: return launch_final_t<4>(bin, blocks, waves, g, sa, lib, ws, out, s);
+    }
+}
+
+template <int NS, int C>
+static int dock_occ(int bin, int waves) {
+    int nb = 0;
+    const size_t lds = dock_lds_bytes(bin_nmax(bin), waves);
+    hipFuncSetAttribute((const void *)k_dock<NS, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_dock<NS, C>, 64 * waves, lds) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int NS>
+static int dock_occ_c(int bin, int waves, int T) {
+    const int C = (T + 63) / 64;
+    if (C <= 1) return dock_occ<NS, 1>(bin, waves);
+    if (C <= 2) return dock_occ<NS, 2>(bin, waves);
+    if (C <= 4) return dock_occ<NS, 4>(bin, waves);
+    if (C <= 8) return dock_occ<NS, 8>(bin, waves);
+    return dock_occ<NS, 16>(bin, waves);
+}
+
+int dock_blocks_per_cu(int bin, int waves, int T) {
+    switch (bin_slots(bin)) {
+        case 1: return dock_occ_c<1>(bin, waves, T);
+        case 2: return dock_occ_c<2>(bin, waves, T);
+        case 3: return dock_occ_c<3>(bin, waves, T);
+        default: return dock_occ_c<4>(bin, waves, T);
+    }
+}
+
+template <int NS>
+static int final_occ(int bin, int waves, int R, int K) {
+    int nb = 0;
+    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, R, K);
+    hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_final<NS>, 64 * waves, lds) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int final_blocks_per_cu(int bin, int waves, int R, int K) {
+    switch (bin_slots(bin)) {
+        case 1: return final_occ<1>(bin, waves, R, K);
+        case 2: return final_occ<2>(bin, waves, R, K);
+        case 3: return final_occ<3>(bin, waves, R, K);
+        default: return final_occ<4>(bin, waves, R, K);
+    }
+}
+
+}  // namespace dockgpu

@@ -1,0 +1,90 @@
+// dock_internal.h -- argument blocks shared by the HIP kernels (dock_device.hip)
+// and the host runtime (dock_runtime.cpp).  Not part of the public ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace dockgpu {
+
+constexpr int kMaxAtoms = 256;      // 4 slots of 64 lanes
+constexpr int kMaxRot = 64;
+constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+1)
+constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
+constexpr uint16_t kTraceNone = 0xFFFFu;
+
+struct GridArgs {
+    const float *values;   // [ntypes][nz][ny][nx]
+    uint32_t bytes;        // total bytes of values
+    uint32_t type_bytes;   // nx*ny*nz*4
+    uint32_t row_bytes;    // nx*4
+    uint32_t slab_bytes;   // nx*ny*4
+    int ntypes, nx, ny, nz;
+    float inv_h;
+    float ox, oy, oz;      // origin
+    float cx, cy, cz;      // grid centre
+    float mx, my, mz;      // n-1 per axis
+    float m2x, m2y, m2z;   // n-2 per axis
+    float fnx, fslab;      // nx and nx*ny as floats
+};
+
+struct SearchArgs {
+    int R, T, P, A, K, final_align, bmin;
+    float bump2g;          // (bump_dist / spacing)^2, grid units
+    float dedup2;          // dedup_rmsd^2, Angstrom^2
+    const float4 *smat;    // [R][3] start rotation rows (x,y,z,0)
+    const float4 *amat;    // [A*A][3] alignment rotation rows
+    const float2 *tors;    // [T] (cos, sin) of 2 pi k / T
+};
+
+struct LibArgs {
+    int L, mask_words;
+    long long A_total, Nb_total, Nr_total;
+    const int *atom_off;
+    const float *xyz;
+    const uint8_t *type;
+    const int *bond_off;
+    const int *bond;
+    const int *rot_off;
+    const int *rot_bond;
+    const unsigned long long *rot_mask;
+};
+
+struct WorkArgs {
+    unsigned long long *far;  // [A_total][kFarWords]
+    int *counters;            // [3*kNumBins]: bin_count, dock_next, final_next
+    int *bin_list;            // [kNumBins][L]
+    float *rscore;            // [L][R]
+    uint16_t *rtrace;         // [R*(L + P*Nr_total)]
+    float *acc_pose;          // [A_total*K*3] kept poses before the final step
+};
+
+struct OutArgs {
+    float *best;
+    int *npose;
+    int *status;
+    float *pscore;
+    int *prestart;
+    float *pxyz;
+    float *rscore_user;       // optional copy of restart scores
+    uint16_t *ftrace;         // optional
+};
+
+// Shared-memory bytes of the docking kernel for a bin with at most nmax atoms
+// and `waves` wavefronts per workgroup.
+size_t dock_lds_bytes(int nmax, int waves);
+size_t final_lds_bytes(int nmax, int waves, int R, int K);
+
+// Launchers (return hipError_t of the launch).
+hipError_t launch_reset(int *counters, hipStream_t s);
+hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                       const WorkArgs &ws, const OutArgs &out, hipStream_t s);
+hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                       const LibArgs &lib, const WorkArgs &ws, hipStream_t s);
+hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out,
+                        hipStream_t s);
+// Max resident workgroups per CU for a launch shape (occupancy API).
+int dock_blocks_per_cu(int bin, int waves, int T);
+int final_blocks_per_cu(int bin, int waves, int R, int K);
+
+}  // namespace dockgpu

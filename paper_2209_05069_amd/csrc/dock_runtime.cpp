@@ -1,0 +1,658 @@
+// dock_runtime.cpp -- host side of the C ABI declared in include/dock.h.
+//
+// Responsibilities: argument checks, pocket residency (one device copy of each
+// pocket's grids, shared by all work; the paper keeps the pocket read-only and
+// shared by every host thread of a GPU), the small per-call tables (start
+// rotations, alignment rotations, torsion cos/sin, computed in double and
+// rounded to float), per-stream workspaces, the launch sequence
+// (reset -> prep -> dock per size bin -> select/final per size bin), and the
+// asynchronous submit/poll path with free-memory admission.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+#include <chrono>
+#include <thread>
+
+#include "dock.h"
+#include "dock_internal.h"
+
+using namespace dockgpu;
+
+namespace {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string &msg) {
+    g_err = msg;
+    return code;
+}
+
+#define HIP_TRY(expr)                                                                \
+    do {                                                                             \
+        hipError_t e_ = (expr);                                                      \
+        if (e_ != hipSuccess)                                                        \
+            return fail(DOCK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+struct Pocket {
+    float *d_values = nullptr;
+    GridArgs g{};
+    int busy = 0;
+};
+
+struct Workspace {
+    void *base = nullptr;
+    size_t bytes = 0;
+};
+
+struct Tables {
+    void *d = nullptr;
+    const float4 *smat = nullptr;
+    const float4 *amat = nullptr;
+    const float2 *tors = nullptr;
+};
+
+struct Ticket {
+    hipEvent_t done = nullptr;
+    int32_t pocket = -1;
+    dock_results user{};
+    int L = 0, K = 0, R = 0;
+    long long A = 0, trace_len = 0;
+    void *host_stage = nullptr;      // pinned copy of the results
+    size_t stage_bytes = 0;
+    // offsets of the result arrays inside host_stage
+    size_t o_best, o_np, o_st, o_ps, o_pr, o_xyz, o_rs, o_tr, o_ft;
+};
+
+}  // namespace
+
+struct dock_ctx {
+    int device = 0;
+    int num_cu = 0;
+    std::mutex mu;
+    std::map<int32_t, Pocket> pockets;
+    int32_t next_pocket = 1;
+    std::map<hipStream_t, Workspace> ws;
+    std::map<std::string, Tables> tables;
+    std::map<std::string, int> occ;
+    hipStream_t submit_stream = nullptr;
+    std::map<uint64_t, Ticket> tickets;
+    uint64_t next_ticket = 1;
+    size_t reserve_bytes = (size_t)1 << 30;
+};
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+int check_params(const dock_params *p) {
+    if (!p) return fail(DOCK_EINVAL, "params is NULL");
+    if (p->restarts < 1 || p->restarts > 4096) return fail(DOCK_EINVAL, "restarts must be in [1,4096]");
+    if (p->torsion_steps < 1 || p->torsion_steps > DOCK_MAX_TORSION_STEPS)
+        return fail(DOCK_EINVAL, "torsion_steps must be in [1,1024]");
+    if (p->sweep_passes < 0 || p->sweep_passes > 16) return fail(DOCK_EINVAL, "sweep_passes must be in [0,16]");
+    if (p->align_steps < 1 || p->align_steps > DOCK_MAX_ALIGN_STEPS)
+        return fail(DOCK_EINVAL, "align_steps must be in [1,255]");
+    if (p->top_k < 1 || p->top_k > DOCK_MAX_TOP_K) return fail(DOCK_EINVAL, "top_k must be in [1,64]");
+    if (p->final_align != 0 && p->final_align != 1) return fail(DOCK_EINVAL, "final_align must be 0 or 1");
+    if (p->bump_min_bonds < 1 || p->bump_min_bonds > DOCK_MAX_ATOMS)
+        return fail(DOCK_EINVAL, "bump_min_bonds must be in [1,256]");
+    if (!(p->bump_dist >= 0.f) || !std::isfinite(p->bump_dist)) return fail(DOCK_EINVAL, "bump_dist must be finite and >= 0");
+    if (!(p->dedup_rmsd >= 0.f) || !std::isfinite(p->dedup_rmsd)) return fail(DOCK_EINVAL, "dedup_rmsd must be finite and >= 0");
+    if (p->mode != DOCK_MODE_BATCHED && p->mode != DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "unknown mode");
+    if (p->mode == DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "plain mode is not available in this build");
+    if (!p->start_quat) return fail(DOCK_EINVAL, "start_quat is NULL");
+    for (int r = 0; r < p->restarts; ++r) {
+        double s = 0;
+        for (int a = 0; a < 4; ++a) {
+            const double v = p->start_quat[4 * r + a];
+            if (!std::isfinite(v)) return fail(DOCK_EINVAL, "start_quat has a non-finite value");
+            s += v * v;
+        }
+        if (s < 1e-12) return fail(DOCK_EINVAL, "start_quat has a zero quaternion");
+    }
+    return DOCK_OK;
+}
+
+int check_library_shape(const dock_library *lib) {
+    if (!lib) return fail(DOCK_EINVAL, "library is NULL");
+    if (lib->n_ligands < 0) return fail(DOCK_EINVAL, "n_ligands < 0");
+    if (lib->mask_words < 1 || lib->mask_words > 4) return fail(DOCK_EINVAL, "mask_words must be in [1,4]");
+    if (lib->n_atoms_total < 0 || lib->n_bonds_total < 0 || lib->n_rot_total < 0)
+        return fail(DOCK_EINVAL, "negative totals");
+    if (lib->n_atoms_total > ((long long)1 << 31) / 64) return fail(DOCK_EINVAL, "n_atoms_total too large");
+    if (lib->n_ligands > 0) {
+        if (!lib->atom_off || !lib->bond_off || !lib->rot_off)
+            return fail(DOCK_EINVAL, "offset array is NULL");
+        if (lib->n_atoms_total > 0 && (!lib->xyz || !lib->type)) return fail(DOCK_EINVAL, "xyz/type is NULL");
+        if (lib->n_bonds_total > 0 && !lib->bond) return fail(DOCK_EINVAL, "bond is NULL");
+        if (lib->n_rot_total > 0 && (!lib->rot_bond || !lib->rot_mask))
+            return fail(DOCK_EINVAL, "rot_bond/rot_mask is NULL");
+    }
+    return DOCK_OK;
+}
+
+int check_results(const dock_results *o, int n_ligands) {
+    if (!o) return fail(DOCK_EINVAL, "results is NULL");
+    if (n_ligands > 0 && (!o->best_score || !o->n_poses || !o->status || !o->pose_score ||
+                          !o->pose_restart || !o->pose_xyz))
+        return fail(DOCK_EINVAL, "a required result array is NULL");
+    return DOCK_OK;
+}
+
+// Start rotations (quaternion -> matrix), alignment rotations R_y(beta_j) R_x(alpha_i),
+// torsion (cos, sin): computed in double, rounded to float.
+int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
+    const int R = p->restarts, A = p->align_steps, T = p->torsion_steps;
+    std::string key((const char *)p->start_quat, sizeof(float) * 4 * (size_t)R);
+    key += "|" + std::to_string(R) + "|" + std::to_string(A) + "|" + std::to_string(T);
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        *out = it->second;
+        return DOCK_OK;
+    }
+    const size_t nS = (size_t)R * 3, nA = (size_t)A * A * 3;
+    std::vector<float4> smat(nS), amat(nA);
+    std::vector<float2> tors(T);
+    for (int r = 0; r < R; ++r) {
+        double w = p->start_quat[4 * r], x = p->start_quat[4 * r + 1], y = p->start_quat[4 * r + 2],
+               z = p->start_quat[4 * r + 3];
+        const double s = std::sqrt(w * w + x * x + y * y + z * z);
+        w /= s; x /= s; y /= s; z /= s;
+        const double M[9] = {1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                             2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                             2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)};
+        for (int a = 0; a < 3; ++a)
+            smat[3 * r + a] = make_float4((float)M[3 * a], (float)M[3 * a + 1], (float)M[3 * a + 2], 0.f);
+    }
+    for (int i = 0; i < A; ++i)
+        for (int j = 0; j < A; ++j) {
+            const double al = 2.0 * M_PI * i / A, be = 2.0 * M_PI * j / A;
+            const double ca = std::cos(al), sa = std::sin(al), cb = std::cos(be), sb = std::sin(be);
+            // R_y(b) R_x(a) = [[cb, sb sa, sb ca], [0, ca, -sa], [-sb, cb sa, cb ca]]
+            const double M[9] = {cb, sb * sa, sb * ca, 0.0, ca, -sa, -sb, cb * sa, cb * ca};
+            const int o = i * A + j;
+            for (int a = 0; a < 3; ++a)
+                amat[3 * o + a] = make_float4((float)M[3 * a], (float)M[3 * a + 1], (float)M[3 * a + 2], 0.f);
+        }
+    for (int k = 0; k < T; ++k) {
+        const double th = 2.0 * M_PI * k / T;
+        tors[k] = make_float2((float)std::cos(th), (float)std::sin(th));
+    }
+    const size_t bS = align256(nS * sizeof(float4)), bA = align256(nA * sizeof(float4)),
+                 bT = align256((size_t)T * sizeof(float2));
+    void *d = nullptr;
+    HIP_TRY(hipMalloc(&d, bS + bA + bT));
+    HIP_TRY(hipMemcpy(d, smat.data(), nS * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((char *)d + bS, amat.data(), nA * sizeof(float4), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((char *)d + bS + bA, tors.data(), (size_t)T * sizeof(float2), hipMemcpyHostToDevice));
+    Tables t;
+    t.d = d;
+    t.smat = (const float4 *)d;
+    t.amat = (const float4 *)((char *)d + bS);
+    t.tors = (const float2 *)((char *)d + bS + bA);
+    c->tables[key] = t;
+    *out = t;
+    return DOCK_OK;
+}
+
+struct WsLayout {
+    size_t far, counters, bin_list, rscore, rtrace, acc, total;
+};
+
+WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trace) {
+    WsLayout w{};
+    size_t o = 0;
+    const size_t L = (size_t)lib->n_ligands, R = (size_t)p->restarts, K = (size_t)p->top_k;
+    w.far = o; o += align256((size_t)lib->n_atoms_total * kFarWords * 8);
+    w.counters = o; o += align256(3 * kNumBins * sizeof(int));
+    w.bin_list = o; o += align256((size_t)kNumBins * L * sizeof(int));
+    w.rscore = o; o += align256(L * R * sizeof(float));
+    w.rtrace = o;
+    if (!user_trace) o += align256(R * (L + (size_t)p->sweep_passes * lib->n_rot_total) * sizeof(uint16_t));
+    w.acc = o; o += align256((size_t)lib->n_atoms_total * K * 3 * sizeof(float));
+    w.total = o;
+    return w;
+}
+
+int get_workspace(dock_ctx *c, hipStream_t s, size_t bytes, void **out) {
+    Workspace &w = c->ws[s];
+    if (w.bytes < bytes) {
+        if (w.base) {
+            HIP_TRY(hipStreamSynchronize(s));
+            HIP_TRY(hipFree(w.base));
+            w.base = nullptr;
+            w.bytes = 0;
+        }
+        const size_t nb = bytes + bytes / 4;
+        if (hipMalloc(&w.base, nb) != hipSuccess) {
+            w.base = nullptr;
+            if (hipMalloc(&w.base, bytes) != hipSuccess) {
+                w.base = nullptr;
+                (void)hipGetLastError();
+                return fail(DOCK_ENOMEM, "workspace allocation failed");
+            }
+            w.bytes = bytes;
+        } else {
+            w.bytes = nb;
+        }
+    }
+    *out = w.base;
+    return DOCK_OK;
+}
+
+int occupancy(dock_ctx *c, const std::string &key, int v) {
+    auto it = c->occ.find(key);
+    if (it != c->occ.end()) return it->second;
+    c->occ[key] = v;
+    return v;
+}
+
+constexpr int kDockWaves = 4;
+constexpr int kFinalWaves = 4;
+
+// Enqueue the whole pipeline for a device-resident library.
+int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
+                  const dock_results *o, hipStream_t s) {
+    if (lib->n_ligands == 0) return DOCK_OK;
+    Tables tb;
+    int rc = get_tables(c, p, &tb);
+    if (rc) return rc;
+    const bool user_trace = o->trace != nullptr;
+    const WsLayout wl = ws_layout(lib, p, user_trace);
+    void *wb = nullptr;
+    rc = get_workspace(c, s, wl.total, &wb);
+    if (rc) return rc;
+    char *base = (char *)wb;
+
+    GridArgs g = pk.g;
+    SearchArgs sa{};
+    sa.R = p->restarts;
+    sa.T = p->torsion_steps;
+    sa.P = p->sweep_passes;
+    sa.A = p->align_steps;
+    sa.K = p->top_k;
+    sa.final_align = p->final_align;
+    sa.bmin = p->bump_min_bonds;
+    {
+        const double bg = (double)p->bump_dist * (double)g.inv_h;
+        sa.bump2g = (float)(bg * bg);
+        sa.dedup2 = (float)((double)p->dedup_rmsd * (double)p->dedup_rmsd);
+    }
+    sa.smat = tb.smat;
+    sa.amat = tb.amat;
+    sa.tors = tb.tors;
+
+    LibArgs la{};
+    la.L = lib->n_ligands;
+    la.mask_words = lib->mask_words;
+    la.A_total = lib->n_atoms_total;
+    la.Nb_total = lib->n_bonds_total;
+    la.Nr_total = lib->n_rot_total;
+    la.atom_off = lib->atom_off;
+    la.xyz = lib->xyz;
+    la.type = lib->type;
+    la.bond_off = lib->bond_off;
+    la.bond = lib->bond;
+    la.rot_off = lib->rot_off;
+    la.rot_bond = lib->rot_bond;
+    la.rot_mask = (const unsigned long long *)lib->rot_mask;
+
+    WorkArgs wa{};
+    wa.far = (unsigned long long *)(base + wl.far);
+    wa.counters = (int *)(base + wl.counters);
+    wa.bin_list = (int *)(base + wl.bin_list);
+    wa.rscore = (float *)(base + wl.rscore);
+    wa.rtrace = user_trace ? o->trace : (uint16_t *)(base + wl.rtrace);
+    wa.acc_pose = (float *)(base + wl.acc);
+
+    OutArgs oa{};
+    oa.best = o->best_score;
+    oa.npose = o->n_poses;
+    oa.status = o->status;
+    oa.pscore = o->pose_score;
+    oa.prestart = o->pose_restart;
+    oa.pxyz = o->pose_xyz;
+    oa.rscore_user = o->restart_score;
+    oa.ftrace = o->final_trace;
+
+    HIP_TRY(launch_reset(wa.counters, s));
+    HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(kDockWaves) + "/" +
+                              std::to_string((sa.T + 63) / 64);
+        const int per_cu = occupancy(c, k, dock_blocks_per_cu(bin, kDockWaves, sa.T));
+        HIP_TRY(launch_dock(bin, per_cu * c->num_cu, kDockWaves, g, sa, la, wa, s));
+    }
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        const std::string k = "f" + std::to_string(bin) + "/" + std::to_string(kFinalWaves) + "/" +
+                              std::to_string(sa.R) + "/" + std::to_string(sa.K);
+        const int per_cu = occupancy(c, k, final_blocks_per_cu(bin, kFinalWaves, sa.R, sa.K));
+        int blocks = per_cu * c->num_cu;
+        if (blocks > la.L) blocks = la.L;
+        HIP_TRY(launch_final(bin, blocks, kFinalWaves, g, sa, la, wa, oa, s));
+    }
+    return DOCK_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char *dock_last_error(void) { return g_err.c_str(); }
+
+int dock_create(int device, dock_ctx **out) {
+    if (!out) return fail(DOCK_EINVAL, "out is NULL");
+    *out = nullptr;
+    int n = 0;
+    HIP_TRY(hipGetDeviceCount(&n));
+    if (device < 0 || device >= n) return fail(DOCK_EINVAL, "no such device");
+    HIP_TRY(hipSetDevice(device));
+    hipDeviceProp_t prop;
+    HIP_TRY(hipGetDeviceProperties(&prop, device));
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0)
+        return fail(DOCK_EDEVICE, std::string("library is built for gfx950, device is ") + prop.gcnArchName);
+    auto *c = new (std::nothrow) dock_ctx();
+    if (!c) return fail(DOCK_ENOMEM, "context allocation failed");
+    c->device = device;
+    c->num_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->submit_stream, hipStreamNonBlocking) != hipSuccess) {
+        delete c;
+        return fail(DOCK_EDEVICE, "stream creation failed");
+    }
+    *out = c;
+    g_err.clear();
+    return DOCK_OK;
+}
+
+int dock_destroy(dock_ctx *c) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    hipSetDevice(c->device);
+    hipDeviceSynchronize();
+    for (auto &kv : c->tickets) {
+        if (kv.second.done) hipEventDestroy(kv.second.done);
+        if (kv.second.host_stage) hipHostFree(kv.second.host_stage);
+    }
+    for (auto &kv : c->pockets) hipFree(kv.second.d_values);
+    for (auto &kv : c->ws) hipFree(kv.second.base);
+    for (auto &kv : c->tables) hipFree(kv.second.d);
+    if (c->submit_stream) hipStreamDestroy(c->submit_stream);
+    delete c;
+    return DOCK_OK;
+}
+
+int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) {
+    if (!c || !gd || !pocket_id) return fail(DOCK_EINVAL, "NULL argument");
+    if (gd->ntypes < 1 || gd->ntypes > 255) return fail(DOCK_EINVAL, "ntypes must be in [1,255]");
+    if (gd->nx < 2 || gd->ny < 2 || gd->nz < 2) return fail(DOCK_EINVAL, "grid dims must be >= 2");
+    const long long cells = (long long)gd->nx * gd->ny * gd->nz;
+    if (cells >= (1LL << 24)) return fail(DOCK_EINVAL, "nx*ny*nz must be < 2^24");
+    const long long bytes = cells * 4 * gd->ntypes;
+    if (bytes >= (1LL << 32)) return fail(DOCK_EINVAL, "grid larger than 4 GiB");
+    if (!(gd->spacing > 0.f) || !std::isfinite(gd->spacing)) return fail(DOCK_EINVAL, "spacing must be > 0");
+    for (int a = 0; a < 3; ++a)
+        if (!std::isfinite(gd->origin[a])) return fail(DOCK_EINVAL, "origin must be finite");
+    if (!gd->values) return fail(DOCK_EINVAL, "values is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    Pocket pk;
+    if (hipMalloc(&pk.d_values, (size_t)bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DOCK_ENOMEM, "pocket allocation failed");
+    }
+    if (hipMemcpy(pk.d_values, gd->values, (size_t)bytes, hipMemcpyHostToDevice) != hipSuccess) {
+        hipFree(pk.d_values);
+        return fail(DOCK_EDEVICE, "pocket copy failed");
+    }
+    GridArgs &g = pk.g;
+    g.values = pk.d_values;
+    g.bytes = (uint32_t)bytes;
+    g.type_bytes = (uint32_t)(cells * 4);
+    g.row_bytes = (uint32_t)gd->nx * 4;
+    g.slab_bytes = (uint32_t)gd->nx * gd->ny * 4;
+    g.ntypes = gd->ntypes;
+    g.nx = gd->nx;
+    g.ny = gd->ny;
+    g.nz = gd->nz;
+    g.inv_h = (float)(1.0 / (double)gd->spacing);
+    g.ox = gd->origin[0];
+    g.oy = gd->origin[1];
+    g.oz = gd->origin[2];
+    g.cx = (float)((double)gd->origin[0] + (double)gd->spacing * (gd->nx - 1) / 2.0);
+    g.cy = (float)((double)gd->origin[1] + (double)gd->spacing * (gd->ny - 1) / 2.0);
+    g.cz = (float)((double)gd->origin[2] + (double)gd->spacing * (gd->nz - 1) / 2.0);
+    g.mx = (float)(gd->nx - 1);
+    g.my = (float)(gd->ny - 1);
+    g.mz = (float)(gd->nz - 1);
+    g.m2x = (float)(gd->nx - 2);
+    g.m2y = (float)(gd->ny - 2);
+    g.m2z = (float)(gd->nz - 2);
+    g.fnx = (float)gd->nx;
+    g.fslab = (float)((long long)gd->nx * gd->ny);
+    const int32_t id = c->next_pocket++;
+    c->pockets[id] = pk;
+    *pocket_id = id;
+    return DOCK_OK;
+}
+
+int dock_pocket_unload(dock_ctx *c, int32_t pocket_id) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket_id);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    if (it->second.busy) return fail(DOCK_EBUSY, "pocket has submitted work in flight");
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());
+    hipFree(it->second.d_values);
+    c->pockets.erase(it);
+    return DOCK_OK;
+}
+
+int dock_ligands_batch(dock_ctx *c, int32_t pocket, const dock_library *lib,
+                       const dock_params *p, dock_results *o, void *stream) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    int rc = check_params(p);
+    if (rc) return rc;
+    rc = check_library_shape(lib);
+    if (rc) return rc;
+    rc = check_results(o, lib->n_ligands);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    HIP_TRY(hipSetDevice(c->device));
+    return enqueue_batch(c, it->second, lib, p, o, (hipStream_t)stream);
+}
+
+int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock_params *p,
+                dock_results *o, uint64_t *ticket) {
+    if (!c || !ticket) return fail(DOCK_EINVAL, "NULL argument");
+    int rc = check_params(p);
+    if (rc) return rc;
+    rc = check_library_shape(lib);
+    if (rc) return rc;
+    rc = check_results(o, lib->n_ligands);
+    if (rc) return rc;
+    const int L = lib->n_ligands;
+    if (L > 0 && (lib->atom_off[L] != lib->n_atoms_total || lib->bond_off[L] != lib->n_bonds_total ||
+                  lib->rot_off[L] != lib->n_rot_total))
+        return fail(DOCK_EINVAL, "offset totals differ from the declared totals");
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    HIP_TRY(hipSetDevice(c->device));
+    const long long A = lib->n_atoms_total, Nb = lib->n_bonds_total, Nr = lib->n_rot_total;
+    const int K = p->top_k, R = p->restarts;
+    const long long trace_len = o->trace ? (long long)R * (L + (long long)p->sweep_passes * Nr) : 0;
+    // device copy of the library and of the results, one allocation
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+    const size_t i_ao = take((size_t)(L + 1) * 4), i_xyz = take((size_t)A * 12), i_ty = take((size_t)A),
+                 i_bo = take((size_t)(L + 1) * 4), i_b = take((size_t)Nb * 8), i_ro = take((size_t)(L + 1) * 4),
+                 i_rb = take((size_t)Nr * 8), i_rm = take((size_t)Nr * lib->mask_words * 8);
+    Ticket t;
+    t.L = L; t.K = K; t.R = R; t.A = A; t.trace_len = trace_len;
+    size_t so = 0;
+    auto stake = [&](size_t b) { size_t r = so; so += align256(b); return r; };
+    t.o_best = stake((size_t)L * 4);
+    t.o_np = stake((size_t)L * 4);
+    t.o_st = stake((size_t)L * 4);
+    t.o_ps = stake((size_t)L * K * 4);
+    t.o_pr = stake((size_t)L * K * 4);
+    t.o_xyz = stake((size_t)A * K * 12);
+    t.o_rs = stake(o->restart_score ? (size_t)L * R * 4 : 0);
+    t.o_tr = stake((size_t)trace_len * 2);
+    t.o_ft = stake(o->final_trace ? (size_t)L * K * 2 : 0);
+    t.stage_bytes = so;
+    const size_t dev_bytes = off + so;
+    // admission: library + results + workspace must fit in free memory less a reserve
+    {
+        const WsLayout wl = ws_layout(lib, p, o->trace != nullptr);
+        size_t freeb = 0, totalb = 0;
+        HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+        const size_t have_ws = c->ws.count(c->submit_stream) ? c->ws[c->submit_stream].bytes : 0;
+        const size_t need = dev_bytes + (wl.total > have_ws ? wl.total : 0);
+        if (need + c->reserve_bytes > freeb) return fail(DOCK_EAGAIN, "not enough free device memory");
+    }
+    hipStream_t s = c->submit_stream;
+    char *d = nullptr;
+    if (hipMallocAsync((void **)&d, dev_bytes > 0 ? dev_bytes : 256, s) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DOCK_EAGAIN, "device allocation failed");
+    }
+    if (hipHostMalloc(&t.host_stage, so > 0 ? so : 256, hipHostMallocDefault) != hipSuccess) {
+        hipFreeAsync(d, s);
+        return fail(DOCK_ENOMEM, "pinned staging allocation failed");
+    }
+    // inputs: copied before return (pageable source -> the copy completes before the call returns)
+    auto up = [&](size_t at, const void *src, size_t b) -> hipError_t {
+        if (b == 0) return hipSuccess;
+        return hipMemcpyAsync(d + at, src, b, hipMemcpyHostToDevice, s);
+    };
+    hipError_t e = hipSuccess;
+    if (L > 0) {
+        e = up(i_ao, lib->atom_off, (size_t)(L + 1) * 4);
+        if (!e) e = up(i_xyz, lib->xyz, (size_t)A * 12);
+        if (!e) e = up(i_ty, lib->type, (size_t)A);
+        if (!e) e = up(i_bo, lib->bond_off, (size_t)(L + 1) * 4);
+        if (!e) e = up(i_b, lib->bond, (size_t)Nb * 8);
+        if (!e) e = up(i_ro, lib->rot_off, (size_t)(L + 1) * 4);
+        if (!e) e = up(i_rb, lib->rot_bond, (size_t)Nr * 8);
+        if (!e) e = up(i_rm, lib->rot_mask, (size_t)Nr * lib->mask_words * 8);
+    }
+    if (!e) e = hipStreamSynchronize(s);  // caller may free its inputs after return
+    if (e) {
+        hipFreeAsync(d, s);
+        hipHostFree(t.host_stage);
+        return fail(DOCK_EDEVICE, std::string("input copy failed: ") + hipGetErrorString(e));
+    }
+    dock_library dl = *lib;
+    dl.atom_off = (const int32_t *)(d + i_ao);
+    dl.xyz = (const float *)(d + i_xyz);
+    dl.type = (const uint8_t *)(d + i_ty);
+    dl.bond_off = (const int32_t *)(d + i_bo);
+    dl.bond = (const int32_t *)(d + i_b);
+    dl.rot_off = (const int32_t *)(d + i_ro);
+    dl.rot_bond = (const int32_t *)(d + i_rb);
+    dl.rot_mask = (const uint64_t *)(d + i_rm);
+    char *dr = d + off;
+    dock_results dres{};
+    dres.best_score = (float *)(dr + t.o_best);
+    dres.n_poses = (int32_t *)(dr + t.o_np);
+    dres.status = (int32_t *)(dr + t.o_st);
+    dres.pose_score = (float *)(dr + t.o_ps);
+    dres.pose_restart = (int32_t *)(dr + t.o_pr);
+    dres.pose_xyz = (float *)(dr + t.o_xyz);
+    dres.restart_score = o->restart_score ? (float *)(dr + t.o_rs) : nullptr;
+    dres.trace = o->trace ? (uint16_t *)(dr + t.o_tr) : nullptr;
+    dres.final_trace = o->final_trace ? (uint16_t *)(dr + t.o_ft) : nullptr;
+    int rc2 = enqueue_batch(c, it->second, &dl, p, &dres, s);
+    if (rc2) {
+        hipStreamSynchronize(s);
+        hipFreeAsync(d, s);
+        hipHostFree(t.host_stage);
+        return rc2;
+    }
+    e = hipMemcpyAsync(t.host_stage, dr, so, hipMemcpyDeviceToHost, s);
+    if (!e) e = hipFreeAsync(d, s);
+    if (!e) e = hipEventCreateWithFlags(&t.done, hipEventDisableTiming);
+    if (!e) e = hipEventRecord(t.done, s);
+    if (e) {
+        hipStreamSynchronize(s);
+        hipHostFree(t.host_stage);
+        return fail(DOCK_EDEVICE, std::string("enqueue failed: ") + hipGetErrorString(e));
+    }
+    t.pocket = pocket;
+    t.user = *o;
+    it->second.busy += 1;
+    const uint64_t id = c->next_ticket++;
+    c->tickets[id] = t;
+    *ticket = id;
+    return DOCK_OK;
+}
+
+static int finish_ticket(dock_ctx *c, std::map<uint64_t, Ticket>::iterator it) {
+    Ticket &t = it->second;
+    const char *h = (const char *)t.host_stage;
+    const dock_results &u = t.user;
+    const size_t L = t.L, K = t.K, R = t.R;
+    if (L > 0) {
+        std::memcpy(u.best_score, h + t.o_best, L * 4);
+        std::memcpy(u.n_poses, h + t.o_np, L * 4);
+        std::memcpy(u.status, h + t.o_st, L * 4);
+        std::memcpy(u.pose_score, h + t.o_ps, L * K * 4);
+        std::memcpy(u.pose_restart, h + t.o_pr, L * K * 4);
+        std::memcpy(u.pose_xyz, h + t.o_xyz, (size_t)t.A * K * 12);
+        if (u.restart_score) std::memcpy(u.restart_score, h + t.o_rs, L * R * 4);
+        if (u.trace) std::memcpy(u.trace, h + t.o_tr, (size_t)t.trace_len * 2);
+        if (u.final_trace) std::memcpy(u.final_trace, h + t.o_ft, L * K * 2);
+    }
+    hipEventDestroy(t.done);
+    hipHostFree(t.host_stage);
+    auto pk = c->pockets.find(t.pocket);
+    if (pk != c->pockets.end() && pk->second.busy > 0) pk->second.busy -= 1;
+    c->tickets.erase(it);
+    return DOCK_OK;
+}
+
+int dock_poll(dock_ctx *c, uint64_t ticket, int32_t *done) {
+    if (!c || !done) return fail(DOCK_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->tickets.find(ticket);
+    if (it == c->tickets.end()) return fail(DOCK_ENOENT, "unknown ticket");
+    const hipError_t q = hipEventQuery(it->second.done);
+    if (q == hipErrorNotReady) {
+        *done = 0;
+        return DOCK_OK;
+    }
+    if (q != hipSuccess) return fail(DOCK_EDEVICE, std::string("event query: ") + hipGetErrorString(q));
+    *done = 1;
+    return finish_ticket(c, it);
+}
+
+int dock_wait(dock_ctx *c, uint64_t ticket) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    // Poll under the lock so a concurrent dock_poll cannot retire the ticket
+    // (and destroy its event) while this thread waits on it.
+    for (;;) {
+        {
+            std::lock_guard<std::mutex> lk(c->mu);
+            auto it = c->tickets.find(ticket);
+            if (it == c->tickets.end()) return fail(DOCK_ENOENT, "unknown ticket");
+            const hipError_t q = hipEventQuery(it->second.done);
+            if (q == hipSuccess) return finish_ticket(c, it);
+            if (q != hipErrorNotReady)
+                return fail(DOCK_EDEVICE, std::string("event query: ") + hipGetErrorString(q));
+        }
+        std::this_thread::sleep_for(std::chrono::microseconds(50));
+    }
+}
+
+}  // extern "C"

@@ -1,0 +1,199 @@
+"""GPU parity: the HIP library (through its C ABI) against the FP64 oracle.
+
+Every comparison uses the follow-mode checks of tests/parity.py on seeded
+synthetic inputs.  Marked `gpu`: needs an MI355X and the built libdock.so.
+"""
+import numpy as np
+import pytest
+
+import synth
+from oracle import oracle as O
+from tests import parity
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+@pytest.fixture(scope="module")
+def D():
+    if not torch.cuda.is_available():
+        pytest.fail("no GPU visible")
+    from paper_2209_05069_amd import dock
+    return dock
+
+
+@pytest.fixture(scope="module")
+def ctx(D):
+    c = D.dock_create(0)
+    yield c
+    D.dock_destroy(c)
+
+
+def run_batch(D, ctx, pk, lib, quats, **kw):
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    params = D.SearchParams(quats, **kw)
+    dl = D.DeviceLibrary(lib)
+    res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params,
+                          restart_scores=True, trace=True, final_trace=True)
+    D.dock_ligands_batch(ctx, pid, dl, params, res)
+    torch.cuda.synchronize()
+    h = res.to_host()
+    D.dock_pocket_unload(ctx, pid)
+    return h, params
+
+
+def check_all(D, pk, lib, quats, h, params, ligands=None, label=""):
+    grid = O.Grid.of(pk)
+    stats = {}
+    ligs = range(lib.n_ligands) if ligands is None else ligands
+    for l in ligs:
+        g = D.ligand_outputs(h, l, lib.atom_off, lib.rot_off, params)
+        assert g["status"] == 0, (l, g["status"])
+        parity.check_ligand(grid, O.ligand_from_library(lib, l), quats, params, g, stats)
+    print(f"[parity {label}] {stats}", flush=True)
+    return stats
+
+
+def test_config1_full_parity(D, ctx):
+    pk, lib, q, s = synth.config(1)
+    print("[case] config 1, 8 ligands", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, **s)
+    check_all(D, pk, lib, q, h, params, label="c1")
+
+
+def test_ragged_sizes_and_slots(D, ctx):
+    # sizes spanning every LDS bin and slot count, with ragged wave tails
+    n = [1, 2, 5, 20, 33, 64, 65, 100, 128, 129, 150, 193, 256]
+    b = [0, 0, 1, 3, 5, 8, 4, 12, 16, 10, 20, 24, 30]
+    lib = synth.library_from_sizes(301, n, b)
+    pk = synth.pocket_gaussians(301, 4, 48, 0.5, 60, 6.0)
+    q = synth.start_quats(301, 5)
+    print("[case] ragged sizes", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=100, sweep_passes=2, align_steps=7,
+                          top_k=8, dedup_rmsd=1.0)
+    check_all(D, pk, lib, q, h, params, label="ragged")
+
+
+@pytest.mark.parametrize("T", [1, 10, 64, 65, 1024])
+def test_torsion_step_counts(D, ctx, T):
+    lib = synth.library_uniform(310 + T, 6, (12, 40), (1, 6))
+    pk = synth.pocket_gaussians(310, 4, 32, 0.5, 40, 4.0)
+    q = synth.start_quats(310, 4)
+    print(f"[case] T={T}", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=T, sweep_passes=2, align_steps=12,
+                          top_k=4, dedup_rmsd=0.5)
+    check_all(D, pk, lib, q, h, params, label=f"T{T}")
+
+
+@pytest.mark.parametrize("variant", [
+    dict(bump_min_bonds=3), dict(bump_min_bonds=5, bump_dist=2.4), dict(dedup_rmsd=0.0),
+    dict(final_align=0), dict(top_k=12, dedup_rmsd=3.0), dict(sweep_passes=0)])
+def test_search_variants(D, ctx, variant):
+    lib = synth.library_uniform(320, 5, (15, 45), (2, 7))
+    pk = synth.pocket_gaussians(320, 4, 32, 0.5, 40, 4.0)
+    q = synth.start_quats(320, 10)
+    kw = dict(torsion_steps=64, sweep_passes=2, align_steps=10, top_k=6, dedup_rmsd=1.5)
+    kw.update(variant)
+    print(f"[case] variant {variant}", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, **kw)
+    check_all(D, pk, lib, q, h, params, label=str(variant))
+
+
+def _corrupt(lib):
+    """Copy of lib with ligand 1 given a bad type, 2 a bad mask, 3 a bad bond index."""
+    L = synth.Library(**{k: (getattr(lib, k).copy() if isinstance(getattr(lib, k), np.ndarray)
+                             else getattr(lib, k)) for k in (
+        "atom_off", "xyz", "type", "bond_off", "bonds", "rot_off", "rot_bond", "rot_mask",
+        "mask_words")})
+    L.type[L.atom_off[1]] = 9
+    r2 = L.rot_off[2]
+    L.rot_mask[r2, 0] ^= np.uint64(1) << np.uint64(int(L.rot_bond[r2, 0]))
+    L.bonds[L.bond_off[3], 1] = 500
+    return L
+
+
+def test_invalid_ligands_are_flagged_and_others_unaffected(D, ctx):
+    lib = synth.library_uniform(330, 6, (15, 30), (2, 4))
+    pk = synth.pocket_gaussians(330, 4, 32, 0.5, 40, 4.0)
+    q = synth.start_quats(330, 4)
+    bad = _corrupt(lib)
+    print("[case] invalid ligands", flush=True)
+    h, params = run_batch(D, ctx, pk, bad, q, torsion_steps=32, sweep_passes=1, align_steps=6,
+                          top_k=4)
+    assert list(h["status"]) == [0, 2, 4, 3, 0, 0]
+    for l in (1, 2, 3):
+        assert h["n_poses"][l] == 0 and h["best_score"][l] == -np.inf
+    check_all(D, pk, bad, q, h, params, ligands=[0, 4, 5], label="valid-in-bad-batch")
+    # the oracle rejects the same three ligands
+    for l in (1, 2, 3):
+        assert O.check_ligand(O.Grid.of(pk), O.ligand_from_library(bad, l)) != 0
+
+
+def test_empty_library(D, ctx):
+    lib = synth.library_from_sizes(340, np.zeros(0, np.int32), np.zeros(0, np.int32),
+                                   mask_words=1)
+    pk = synth.pocket_gaussians(340, 4, 16, 0.5, 5, 2.0)
+    q = synth.start_quats(340, 3)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=16, top_k=2)
+    assert h["best_score"].size == 0
+
+
+def test_restarts_fewer_than_top_k_and_rigid_only(D, ctx):
+    lib = synth.library_from_sizes(350, [9, 30, 17], [0, 0, 0])
+    pk = synth.pocket_gaussians(350, 4, 32, 0.5, 40, 4.0)
+    q = synth.start_quats(350, 3)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=16, top_k=8, dedup_rmsd=0.0)
+    assert list(h["n_poses"]) == [3, 3, 3]
+    check_all(D, pk, lib, q, h, params, label="rigid")
+
+
+def test_submit_poll_matches_device_batch_and_is_deterministic(D, ctx):
+    pk, lib, q, s = synth.config(1)
+    h1, params = run_batch(D, ctx, pk, lib, q, **s)
+    h2, _ = run_batch(D, ctx, pk, lib, q, **s)
+    for k in h1:
+        if h1[k] is not None:
+            np.testing.assert_array_equal(h1[k], h2[k], err_msg=k)
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    hr = D.HostResults(lib.n_ligands, int(lib.atom_off[-1]), int(lib.rot_off[-1]), params,
+                       restart_scores=True, trace=True, final_trace=True)
+    t = D.dock_submit(ctx, pid, lib, params, hr)
+    D.dock_wait(ctx, t)
+    with pytest.raises(D.DockError):
+        D.dock_poll(ctx, t)
+    h3 = hr.to_host()
+    for k in h1:
+        if h1[k] is not None:
+            np.testing.assert_array_equal(h1[k], h3[k], err_msg=k)
+    D.dock_pocket_unload(ctx, pid)
+
+
+def test_config2_full_size_sampled(D, ctx):
+    """Full paper-scale workload (10,000 ligands, 96^3 x 4 pocket, R=T=256, P=3,
+    K=30) in the benchmark's launch configuration; sampled ligands checked
+    against the oracle, properties checked on every ligand."""
+    pk, lib, q, s = synth.config(2)
+    print("[case] config 2 full size", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, **s)
+    L = lib.n_ligands
+    assert np.all(h["status"] == 0)
+    assert np.all(h["n_poses"] >= 1)
+    K = params.top_k
+    ps = h["pose_score"].reshape(L, K)
+    assert np.all(h["best_score"] == ps[:, 0])
+    for l in range(L):
+        npz = h["n_poses"][l]
+        assert np.all(np.diff(ps[l, :npz]) <= 0)
+    # every output pose keeps the input bond lengths (rigid moves + torsions only)
+    worst = 0.0
+    for l in range(0, L, 7):
+        x, t, b, r, m = lib.ligand(l)
+        g = D.ligand_outputs(h, l, lib.atom_off, lib.rot_off, params)
+        d0 = np.linalg.norm(x[b[:, 0]] - x[b[:, 1]], axis=1)
+        d1 = np.linalg.norm(g["pose_xyz"][:, b[:, 0]] - g["pose_xyz"][:, b[:, 1]], axis=-1)
+        worst = max(worst, float(np.abs(d1 - d0).max(initial=0)))
+    assert worst < 1e-3, worst
+    rng = np.random.default_rng(2209)
+    sample = sorted(int(v) for v in rng.choice(L, 3, replace=False))
+    check_all(D, pk, lib, q, h, params, ligands=sample, label="c2-sample")
