@@ -197,6 +197,22 @@ int dock_poll(dock_ctx *ctx, uint64_t ticket, int32_t *done);
 /* Block until `ticket` is done, then retire it. */
 int dock_wait(dock_ctx *ctx, uint64_t ticket);
 
+/* Phase timing, for measurement.  While enabled, every dock_ligands_batch
+ * call records HIP events on its own stream before its prep kernel, after it,
+ * after the docking kernels and after the select/final kernels.
+ * dock_get_timing waits for every recorded event, returns the summed
+ * milliseconds of each phase and the number of calls since the last
+ * dock_get_timing, and starts a new sum. */
+typedef struct {
+    double prep_ms;   /* ligand checks, bump-pair rows, size binning */
+    double dock_ms;   /* restarts: start pose, alignment, torsion sweeps */
+    double final_ms;  /* pose selection, final rigid step, outputs */
+    int64_t calls;
+} dock_timing;
+
+int dock_set_timing(dock_ctx *ctx, int enable);
+int dock_get_timing(dock_ctx *ctx, dock_timing *out);
+
 #ifdef __cplusplus
 }
 #endif

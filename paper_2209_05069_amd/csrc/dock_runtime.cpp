@@ -17,6 +17,7 @@
 #include <mutex>
 #include <string>
 #include <vector>
+#include <array>
 #include <chrono>
 #include <thread>
 
@@ -86,6 +87,8 @@ struct dock_ctx {
     std::map<uint64_t, Ticket> tickets;
     uint64_t next_ticket = 1;
     size_t reserve_bytes = (size_t)1 << 30;
+    bool timing = false;
+    std::vector<std::array<hipEvent_t, 4>> marks;  // per call: start, after prep, after dock, end
 };
 
 namespace {
@@ -323,8 +326,15 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     oa.rscore_user = o->restart_score;
     oa.ftrace = o->final_trace;
 
+    std::array<hipEvent_t, 4> ev{};
+    if (c->timing) {
+        for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
+        c->marks.push_back(ev);
+    }
     HIP_TRY(launch_reset(wa.counters, s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[1], s));
     for (int bin = 0; bin < kNumBins; ++bin) {
         const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(kDockWaves) + "/" +
                               std::to_string((sa.T + 63) / 64);
@@ -337,8 +347,10 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         const int per_cu = occupancy(c, k, final_blocks_per_cu(bin, kFinalWaves, sa.R, sa.K));
         int blocks = per_cu * c->num_cu;
         if (blocks > la.L) blocks = la.L;
+        if (bin == 0 && c->timing) HIP_TRY(hipEventRecord(ev[2], s));
         HIP_TRY(launch_final(bin, blocks, kFinalWaves, g, sa, la, wa, oa, s));
     }
+    if (c->timing) HIP_TRY(hipEventRecord(ev[3], s));
     return DOCK_OK;
 }
 
@@ -383,6 +395,8 @@ int dock_destroy(dock_ctx *c) {
     for (auto &kv : c->pockets) hipFree(kv.second.d_values);
     for (auto &kv : c->ws) hipFree(kv.second.base);
     for (auto &kv : c->tables) hipFree(kv.second.d);
+    for (auto &m : c->marks)
+        for (auto &e : m) hipEventDestroy(e);
     if (c->submit_stream) hipStreamDestroy(c->submit_stream);
     delete c;
     return DOCK_OK;
@@ -635,6 +649,35 @@ int dock_poll(dock_ctx *c, uint64_t ticket, int32_t *done) {
     if (q != hipSuccess) return fail(DOCK_EDEVICE, std::string("event query: ") + hipGetErrorString(q));
     *done = 1;
     return finish_ticket(c, it);
+}
+
+int dock_set_timing(dock_ctx *c, int enable) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    c->timing = enable != 0;
+    return DOCK_OK;
+}
+
+int dock_get_timing(dock_ctx *c, dock_timing *out) {
+    if (!c || !out) return fail(DOCK_EINVAL, "NULL argument");
+    std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    dock_timing t{};
+    for (auto &m : c->marks) {
+        HIP_TRY(hipEventSynchronize(m[3]));
+        float a = 0.f, b = 0.f, d = 0.f;
+        HIP_TRY(hipEventElapsedTime(&a, m[0], m[1]));
+        HIP_TRY(hipEventElapsedTime(&b, m[1], m[2]));
+        HIP_TRY(hipEventElapsedTime(&d, m[2], m[3]));
+        t.prep_ms += a;
+        t.dock_ms += b;
+        t.final_ms += d;
+        t.calls += 1;
+        for (auto &e : m) (void)hipEventDestroy(e);
+    }
+    c->marks.clear();
+    *out = t;
+    return DOCK_OK;
 }
 
 int dock_wait(dock_ctx *c, uint64_t ticket) {

@@ -57,8 +57,14 @@ class Results(ctypes.Structure):
                 ("final_trace", P)]
 
 
-EXPORTS = ["dock_create", "dock_destroy", "dock_last_error", "dock_pocket_load",
-           "dock_pocket_unload", "dock_ligands_batch", "dock_submit", "dock_poll", "dock_wait"]
+class Timing(ctypes.Structure):
+    _fields_ = [("prep_ms", ctypes.c_double), ("dock_ms", ctypes.c_double),
+                ("final_ms", ctypes.c_double), ("calls", ctypes.c_int64)]
+
+
+EXPORTS = ["dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
+           "dock_ligands_batch", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
+           "dock_set_timing", "dock_submit", "dock_wait"]
 
 _lib = None
 
@@ -85,6 +91,8 @@ def lib():
                                   ctypes.POINTER(ctypes.c_uint64)]
         L.dock_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
         L.dock_wait.argtypes = [P, ctypes.c_uint64]
+        L.dock_set_timing.argtypes = [P, ctypes.c_int]
+        L.dock_get_timing.argtypes = [P, ctypes.POINTER(Timing)]
         _lib = L
     return _lib
 
@@ -302,6 +310,16 @@ def dock_poll(ctx, ticket: int) -> bool:
 
 def dock_wait(ctx, ticket: int):
     _check(lib().dock_wait(ctx, ticket))
+
+
+def dock_set_timing(ctx, enable: bool):
+    _check(lib().dock_set_timing(ctx, 1 if enable else 0))
+
+
+def dock_get_timing(ctx) -> dict:
+    t = Timing()
+    _check(lib().dock_get_timing(ctx, ctypes.byref(t)))
+    return dict(prep_ms=t.prep_ms, dock_ms=t.dock_ms, final_ms=t.final_ms, calls=t.calls)
 
 
 def trace_offset(l, R, P, rot_off):

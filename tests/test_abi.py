@@ -52,7 +52,8 @@ def test_header_structs_match_binding_layout():
     # field order/size of the ctypes mirrors (checked against the header's fields)
     src = open(HEADER).read()
     for struct, cls in (("dock_library", dock.Library), ("dock_params", dock.Params),
-                        ("dock_results", dock.Results), ("dock_grid_desc", dock.GridDesc)):
+                        ("dock_results", dock.Results), ("dock_grid_desc", dock.GridDesc),
+                        ("dock_timing", dock.Timing)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + ";", src).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []
