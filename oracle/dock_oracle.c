@@ -387,6 +387,11 @@ static int torsion_decision(const ctx_t *C, int b, double *Y, int follow_k, doub
             if (D[k] >= bd + tol && S[k] > best_sure) best_sure = S[k];
         }
         C->stats[0] += 1;
+        /* diagnostic: candidates scoring above the applied one (all bumped when the
+         * applied one is the best bump-free candidate) */
+        if (follow_k >= 0 && follow_k < T)
+            for (int k = 0; k < T; ++k)
+                if (S[k] > S[follow_k]) C->stats[5] += 1;
         if (follow_k == (int)NONE_ACCEPTED) {
             if (best_k < 0) C->stats[1] += 1;
             else if (best_sure == -INFINITY) C->stats[3] += 1;  /* only near-boundary candidates */

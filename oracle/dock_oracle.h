@@ -51,7 +51,8 @@ typedef struct {
     double *pose_score;      /* [top_k] or NULL */
     double *pose_xyz;        /* [top_k][n][3] or NULL */
     uint16_t *final_trace;   /* [top_k] or NULL */
-    /* follow statistics: decisions, exact, score ties, bump ties, mismatches, -, max tie gap, - */
+    /* follow statistics: decisions, exact, score ties, bump ties, mismatches,
+     * candidates scoring above the applied torsion step (summed), max tie gap, - */
     double stats[8];
 } or_result;
 

@@ -238,6 +238,7 @@ def dock_ligand(grid, lig, quats, follow=None, decisions=False, **params):
         out[k] = out[k][:ns].copy()
     st = list(res.stats)
     out["stats"] = dict(decisions=int(st[0]), exact=int(st[1]), score_ties=int(st[2]),
-                        bump_ties=int(st[3]), mismatches=int(st[4]), max_tie_gap=st[6])
+                        bump_ties=int(st[3]), mismatches=int(st[4]), above_applied=int(st[5]),
+                        max_tie_gap=st[6])
     out["best_score"] = float(out["pose_score"][0]) if ns else float("-inf")
     return out

@@ -12,11 +12,13 @@
 //    sit once per wave in LDS (broadcast reads);
 //  * only the moving fragment's score changes with the torsion angle, so the
 //    candidates are ranked by that partial sum (same argmax as the full score);
-//  * best-first bump check: the wave takes the best-scoring candidate (64-bit
-//    key max: order-preserving score bits, then the lower index), checks its
-//    moving-vs-static pairs with lanes over static atoms and a ballot after each
-//    moving atom (early exit), and on a bump drops that candidate and repeats.
-//    This selects exactly the best bump-free candidate;
+//  * bump check in closed form: turning a moving atom about the bond axis makes
+//    its squared distance to a static atom C + A cos(theta) + B sin(theta), so
+//    lanes over static atoms compute (C, A, B) per pair, drop pairs whose
+//    closest approach stays above the bump distance (ballot), and test the few
+//    remaining pairs against every candidate with two FMAs; one 64-bit key max
+//    (order-preserving score bits, then the lower index) over the bump-free
+//    candidates picks the step;
 //  * grid gathers are raw buffer loads: one 32-bit voffset for the cell and the
 //    8 corners as scalar offsets, with the range checked by hardware;
 //  * a persistent grid pops (ligand, restart-group) items from a per-bin queue;
@@ -86,18 +88,22 @@ __device__ __forceinline__ void wave_lds_sync() {
 
 // ---------------------------------------------------------------------------
 // Trilinear interpolation.  (gx,gy,gz) are grid coordinates ((p - origin)/h);
-// each is clamped to [0, n-1], the cell corner is min(floor, n-2).  toff is the
-// byte offset of the atom type's block.
+// each is clamped to [0, n-1], the cell corner is min(floor, n-2).  The pocket
+// is stored as corner quads (see GridArgs), so the 8 corners are two 16-byte
+// loads: the quad of slab k and the quad of slab k+1 (scalar offset slab_bytes).
+// toff is the byte offset of the atom type's block.
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 struct Tri {
     __amdgpu_buffer_rsrc_t rs;
-    uint32_t row, slab;
+    uint32_t slab;
     float mx, my, mz, m2x, m2y, m2z, fnx, fslab;
 };
 
 __device__ __forceinline__ Tri make_tri(const GridArgs &g) {
     Tri t;
-    t.rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.values, (short)0, (int)g.bytes, 0x00020000);
-    t.row = g.row_bytes;
+    t.rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.quads, (short)0,
+                                             (int)(g.nquads * 16u), 0x00020000);
     t.slab = g.slab_bytes;
     t.mx = g.mx; t.my = g.my; t.mz = g.mz;
     t.m2x = g.m2x; t.m2y = g.m2y; t.m2z = g.m2z;
@@ -105,7 +111,7 @@ __device__ __forceinline__ Tri make_tri(const GridArgs &g) {
     return t;
 }
 
-// cell offset (bytes within the type block) and fractions
+// byte offset of the cell's quad within the type block, and the fractions
 __device__ __forceinline__ uint32_t tri_cell(const Tri &t, float gx, float gy, float gz, float &fx,
                                              float &fy, float &fz) {
     const float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
@@ -119,56 +125,62 @@ __device__ __forceinline__ uint32_t tri_cell(const Tri &t, float gx, float gy, f
     fz = cz - iz;
     // element index < 2^24: exact in float
     const float e = fmaf(iz, t.fslab, fmaf(iy, t.fnx, ix));
-    return ((uint32_t)e) << 2;
+    return ((uint32_t)e) << 4;
 }
 
-__device__ __forceinline__ float tri_blend(float v000, float v100, float v010, float v110,
-                                           float v001, float v101, float v011, float v111,
-                                           float fx, float fy, float fz) {
-    const float c00 = fmaf(fx, v100 - v000, v000);
-    const float c10 = fmaf(fx, v110 - v010, v010);
-    const float c01 = fmaf(fx, v101 - v001, v001);
-    const float c11 = fmaf(fx, v111 - v011, v011);
+// 16-byte raw buffer load; the builtin returns the bits as integers.
+__device__ __forceinline__ float4 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t voff, int soff) {
+    const u32x4 v = __builtin_amdgcn_raw_buffer_load_b128(rs, (int)voff, soff, 0);
+    return make_float4(__uint_as_float(v.x), __uint_as_float(v.y), __uint_as_float(v.z),
+                       __uint_as_float(v.w));
+}
+
+__device__ __forceinline__ float tri_blend(const float4 q0, const float4 q1, float fx, float fy,
+                                           float fz) {
+    // q = (v(i,j), v(i+1,j), v(i,j+1), v(i+1,j+1)) of slabs k (q0) and k+1 (q1)
+    const float c00 = fmaf(fx, q0.y - q0.x, q0.x);
+    const float c10 = fmaf(fx, q0.w - q0.z, q0.z);
+    const float c01 = fmaf(fx, q1.y - q1.x, q1.x);
+    const float c11 = fmaf(fx, q1.w - q1.z, q1.z);
     const float c0 = fmaf(fy, c10 - c00, c00);
     const float c1 = fmaf(fy, c11 - c01, c01);
     return fmaf(fz, c1 - c0, c0);
 }
 
-// 32-bit raw buffer load; the builtin returns the bits as an integer.
-__device__ __forceinline__ float ld(__amdgpu_buffer_rsrc_t rs, uint32_t voff, int soff) {
-    return __uint_as_float((uint32_t)__builtin_amdgcn_raw_buffer_load_b32(rs, (int)voff, soff, 0));
-}
-
-// wave-uniform type offset (scalar offsets for the 8 corners)
+// wave-uniform type offset (scalar offsets)
 __device__ __forceinline__ float tri_u(const Tri &t, float gx, float gy, float gz, int toff) {
     float fx, fy, fz;
     const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz);
-    const int r = (int)t.row, s = (int)t.slab;
-    const float v000 = ld(t.rs, off, toff);
-    const float v100 = ld(t.rs, off, toff + 4);
-    const float v010 = ld(t.rs, off, toff + r);
-    const float v110 = ld(t.rs, off, toff + r + 4);
-    const float v001 = ld(t.rs, off, toff + s);
-    const float v101 = ld(t.rs, off, toff + s + 4);
-    const float v011 = ld(t.rs, off, toff + s + r);
-    const float v111 = ld(t.rs, off, toff + s + r + 4);
-    return tri_blend(v000, v100, v010, v110, v001, v101, v011, v111, fx, fy, fz);
+    const float4 q0 = ldq(t.rs, off, toff);
+    const float4 q1 = ldq(t.rs, off, toff + (int)t.slab);
+    return tri_blend(q0, q1, fx, fy, fz);
 }
 
 // per-lane type offset
 __device__ __forceinline__ float tri_v(const Tri &t, float gx, float gy, float gz, uint32_t toff) {
     float fx, fy, fz;
     const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz) + toff;
-    const int r = (int)t.row, s = (int)t.slab;
-    const float v000 = ld(t.rs, off, 0);
-    const float v100 = ld(t.rs, off, 4);
-    const float v010 = ld(t.rs, off, r);
-    const float v110 = ld(t.rs, off, r + 4);
-    const float v001 = ld(t.rs, off, s);
-    const float v101 = ld(t.rs, off, s + 4);
-    const float v011 = ld(t.rs, off, s + r);
-    const float v111 = ld(t.rs, off, s + r + 4);
-    return tri_blend(v000, v100, v010, v110, v001, v101, v011, v111, fx, fy, fz);
+    const float4 q0 = ldq(t.rs, off, 0);
+    const float4 q1 = ldq(t.rs, off, (int)t.slab);
+    return tri_blend(q0, q1, fx, fy, fz);
+}
+
+// Corner quads from the plain grid (one thread per quad).  Quads at i = nx-1 or
+// j = ny-1 are never read (the cell corner is at most n-2); they repeat the edge.
+__global__ void k_build_quads(const float *__restrict__ v, float4 *__restrict__ q, int ntypes,
+                              int nx, int ny, int nz) {
+    const long long cells = (long long)nx * ny * nz;
+    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= cells * ntypes) return;
+    const long long t = e / cells;
+    long long r = e - t * cells;
+    const int k = (int)(r / ((long long)nx * ny));
+    r -= (long long)k * nx * ny;
+    const int j = (int)(r / nx), i = (int)(r - (long long)j * nx);
+    const int i1 = i + 1 < nx ? i + 1 : i, j1 = j + 1 < ny ? j + 1 : j;
+    const float *b = v + t * cells + (long long)k * nx * ny;
+    q[e] = make_float4(b[(long long)j * nx + i], b[(long long)j * nx + i1],
+                       b[(long long)j1 * nx + i], b[(long long)j1 * nx + i1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -255,12 +267,40 @@ __device__ __forceinline__ void apply_align(Pose<NS> &Y, int n, int o, const Sea
     }
 }
 
+// How the candidates of one decision (alignment orientations, torsion steps) are
+// spread and reduced.  WaveSplit: one wavefront holds them all (batched form).
+// BlockSplit: the waves of a workgroup hold interleaved slices and the argmax
+// goes through LDS with workgroup barriers (plain form; every wave keeps the
+// same pose).
+struct WaveSplit {
+    __device__ __forceinline__ int first() const { return 0; }
+    __device__ __forceinline__ int stride() const { return 64; }
+    __device__ __forceinline__ u64 reduce(u64 k) const { return wave_max_u64(k); }
+};
+
+struct BlockSplit {
+    int wave, waves;
+    u64 *slots;  // LDS, [waves]
+    __device__ __forceinline__ int first() const { return 64 * wave; }
+    __device__ __forceinline__ int stride() const { return 64 * waves; }
+    __device__ __forceinline__ u64 reduce(u64 k) const {
+        k = wave_max_u64(k);
+        if (lane_id() == 0) slots[wave] = k;
+        __syncthreads();
+        u64 r = slots[0];
+        for (int w = 1; w < waves; ++w) r = slots[w] > r ? slots[w] : r;
+        __syncthreads();
+        return r;
+    }
+};
+
 // Alignment (Rigid Rotation): lanes over the A*A orientations, loop over atoms.
 // rec: per-wave LDS, >= n float4.  toff[s]: type byte offset of this lane's atoms.
 // Applies and returns the best orientation; *best_out = its score.
-template <int NS>
+template <int NS, class Split>
 __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec, const Tri &tr,
-                          const GridArgs &g, const SearchArgs &sa, float *best_out) {
+                          const GridArgs &g, const SearchArgs &sa, float *best_out,
+                          const Split &sp) {
     const int lane = lane_id();
     float cx, cy, cz;
     centroid(Y, n, cx, cy, cz);
@@ -275,7 +315,7 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
     const float ex = (cx - g.ox) * g.inv_h, ey = (cy - g.oy) * g.inv_h, ez = (cz - g.oz) * g.inv_h;
     const int NO = sa.A * sa.A;
     u64 best = 0;
-    for (int base = 0; base < NO; base += 64) {
+    for (int base = sp.first(); base < NO; base += sp.stride()) {
         const int o = base + lane;
         const bool ov = o < NO;
         const int oo = ov ? o : 0;
@@ -292,7 +332,7 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
         const u64 key = ov ? make_key(acc, (uint32_t)o) : 0ull;
         best = key > best ? key : best;
     }
-    best = wave_max_u64(best);
+    best = sp.reduce(best);
     const int ob = (int)key_index(best);
     if (best_out) *best_out = key_score(best);
     wave_lds_sync();  // rec is rewritten by the caller next
@@ -358,11 +398,11 @@ __device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, int 
 // One torsion decision (Optimize Pose, inner angle loop) for rotatable bond with
 // moving-mask row mrow (NS words), axis atoms (a,b).  cs[c] = (cos,sin) of this
 // lane's candidates k = lane + 64c.  Returns the applied step or kTraceNone.
-template <int NS, int C>
+template <int NS, int C, class Split>
 __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                               const u64 *far, const int (&toff)[NS], float4 *rec,
                               const float2 (&cs)[C], const Tri &tr, const GridArgs &g,
-                              const SearchArgs &sa) {
+                              const SearchArgs &sa, const Split &sp) {
     const int lane = lane_id();
     const Axis A = bond_axis(Y, a, b);
     u64 mw[NS];
@@ -415,52 +455,54 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
             acc[c] += tri_u(tr, gx, gy, gz, to);
         }
     }
-    u64 key[C];
+    // Bump Check of every candidate at once.  For moving atom i (frame P0, V, W)
+    // and static atom j, the squared distance after a turn by theta is
+    //   d2(theta) = Cq + Aq cos(theta) + Bq sin(theta),
+    //   Cq = |P0 - Y_j|^2 + |V|^2, Aq = 2 (P0 - Y_j).V, Bq = 2 (P0 - Y_j).W
+    // (V and W are orthogonal with |V| = |W|).  Its minimum over theta is
+    // Cq - sqrt(Aq^2 + Bq^2); pairs that cannot come closer than the bump distance
+    // are skipped, and each remaining pair is tested against every candidate of
+    // the lane with two FMAs.  Distances are in grid units.
+    bool bumped[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) bumped[c] = false;
+    const float lim = sa.bump2g;
+    const float lim_in = lim * (1.0f + 1e-4f);  // filter margin: keeps borderline pairs
+    for (int q = 0; q < m; ++q) {
+        const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
+        const int i = uniform_int(__float_as_int(r1.w));
+        const float vv = fmaf(r1.x, r1.x, fmaf(r1.y, r1.y, r1.z * r1.z));
+#pragma unroll
+        for (int s = 0; s < NS; ++s) {
+            const u64 fw = far[i * NS + s];
+            const bool el = st[s] && ((fw >> lane) & 1ull);
+            const float dx = r0.x - sgx[s], dy = r0.y - sgy[s], dz = r0.z - sgz[s];
+            const float cq = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, vv)));
+            const float aq = 2.0f * fmaf(dx, r1.x, fmaf(dy, r1.y, dz * r1.z));
+            const float bq = 2.0f * fmaf(dx, r2.x, fmaf(dy, r2.y, dz * r2.z));
+            const float e = cq - lim_in;
+            const bool maybe = el && (e < 0.0f || e * e < fmaf(aq, aq, bq * bq));
+            u64 bal = __ballot(maybe);
+            while (bal != 0ull) {
+                const int src = __ffsll((long long)bal) - 1;
+                bal &= bal - 1ull;
+                const float c0 = read_lane(cq, src), a0 = read_lane(aq, src),
+                            b0 = read_lane(bq, src);
+#pragma unroll
+                for (int c = 0; c < C; ++c)
+                    bumped[c] = bumped[c] || (fmaf(b0, cs[c].y, fmaf(a0, cs[c].x, c0)) < lim);
+            }
+        }
+    }
+    u64 best = 0ull;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
-        const int k = lane + 64 * c;
-        key[c] = k < sa.T ? make_key(acc[c], (uint32_t)k) : 0ull;
+        const int k = sp.first() + lane + sp.stride() * c;
+        const u64 key = (k < sa.T && !bumped[c]) ? make_key(acc[c], (uint32_t)k) : 0ull;
+        best = key > best ? key : best;
     }
-
-    // best-first bump check
-    int kstar = kTraceNone;
-    for (;;) {
-        u64 best = key[0];
-#pragma unroll
-        for (int c = 1; c < C; ++c) best = key[c] > best ? key[c] : best;
-        best = wave_max_u64(best);
-        if (best == 0ull) break;
-        const int k = (int)key_index(best);
-        const float2 t = sa.tors[k];
-        bool bump = false;
-        for (int q = 0; q < m; ++q) {
-            const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
-            const int i = uniform_int(__float_as_int(r1.w));
-            const float zx = fmaf(t.y, r2.x, fmaf(t.x, r1.x, r0.x));
-            const float zy = fmaf(t.y, r2.y, fmaf(t.x, r1.y, r0.y));
-            const float zz = fmaf(t.y, r2.z, fmaf(t.x, r1.z, r0.z));
-            bool hit = false;
-#pragma unroll
-            for (int s = 0; s < NS; ++s) {
-                const u64 fw = far[i * NS + s];
-                const bool el = st[s] && ((fw >> lane) & 1ull);
-                const float dx = zx - sgx[s], dy = zy - sgy[s], dz = zz - sgz[s];
-                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
-                hit = hit || (el && d2 < sa.bump2g);
-            }
-            if (__ballot(hit) != 0ull) {
-                bump = true;
-                break;
-            }
-        }
-        if (!bump) {
-            kstar = k;
-            break;
-        }
-#pragma unroll
-        for (int c = 0; c < C; ++c)
-            if (c == (k >> 6) && lane == (k & 63)) key[c] = 0ull;
-    }
+    best = sp.reduce(best);
+    const int kstar = best == 0ull ? (int)kTraceNone : (int)key_index(best);
     wave_lds_sync();  // rec is rewritten next
     if (kstar != (int)kTraceNone) {
         const float2 t = sa.tors[kstar];
@@ -523,8 +565,8 @@ __device__ void stage_ligand(unsigned char *smem, int nmax, int l, const LibArgs
     const int r0 = lib.rot_off[l], B = lib.rot_off[l + 1] - r0;
     for (int i = threadIdx.x; i < n; i += blockDim.x) {
         const float *p = lib.xyz + 3 * (size_t)(a0 + i);
-        const int toff = (int)lib.type[a0 + i] * (int)g.type_bytes;
-        xyzt[i] = make_float4(p[0], p[1], p[2], __int_as_float(toff));
+        const uint32_t toff = (uint32_t)lib.type[a0 + i] * g.type_bytes;
+        xyzt[i] = make_float4(p[0], p[1], p[2], __uint_as_float(toff));
     }
     if (with_far) {
         for (int e = threadIdx.x; e < n * NS; e += blockDim.x) {
@@ -604,7 +646,7 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
             Pose<NS> Y;
             start_pose(Y, xyzt, n, r, g, sa);
             uint16_t *tr_out = ws.rtrace + trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B);
-            const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr);
+            const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, WaveSplit());
             if (lane == 0) tr_out[0] = (uint16_t)o;
             int d = 1;
             for (int p = 0; p < sa.P; ++p) {
@@ -612,7 +654,7 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
                     const int2 ab = rot[b];
                     const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
                                                         uniform_int(ab.y), far, toff, rec, cs, tr,
-                                                        g, sa);
+                                                        g, sa, WaveSplit());
                     if (lane == 0) tr_out[d] = (uint16_t)k;
                 }
             }
@@ -621,6 +663,57 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
         }
         __syncthreads();
     }
+}
+
+// Plain (latency) form: one ligand per launch sequence.  Workgroup r docks
+// restart r; its waves split the orientations and the torsion candidates and
+// agree on every decision through LDS and workgroup barriers.
+template <int NS, int C>
+__global__ __launch_bounds__(256) void k_plain(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
+                                               const int *__restrict__ status, int l, int bin) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nmax = bin_nmax(bin);
+    const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
+    if (status[l] != 0) return;
+    float4 *xyzt = (float4 *)(smem + Lds::xyzt(nmax));
+    const u64 *far = (const u64 *)(smem + Lds::far(nmax));
+    const u64 *mask = (const u64 *)(smem + Lds::mask(nmax, NS));
+    const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
+    int *misc = (int *)(smem + Lds::misc(nmax, NS));
+    float4 *rec = (float4 *)(smem + Lds::rec(nmax, NS) + (size_t)wave * Lds::rec_stride(nmax));
+    u64 *slots = (u64 *)(smem + Lds::rec(nmax, NS) + (size_t)W * Lds::rec_stride(nmax));
+    const Tri tr = make_tri(g);
+    const BlockSplit sp{wave, W, slots};
+    float2 cs[C];
+#pragma unroll
+    for (int c = 0; c < C; ++c) {
+        const int k = sp.first() + lane + sp.stride() * c;
+        cs[c] = k < sa.T ? sa.tors[k] : make_float2(1.f, 0.f);
+    }
+    stage_ligand<NS>(smem, nmax, l, lib, ws, g, true);
+    __syncthreads();
+    const int r = blockIdx.x;
+    const int n = misc[1], B = misc[2];
+    int toff[NS];
+    lane_toff(xyzt, n, toff);
+    Pose<NS> Y;
+    start_pose(Y, xyzt, n, r, g, sa);
+    uint16_t *tr_out = ws.rtrace + trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B);
+    const bool writer = threadIdx.x == 0;
+    const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, sp);
+    if (writer) tr_out[0] = (uint16_t)o;
+    int d = 1;
+    for (int p = 0; p < sa.P; ++p) {
+        for (int b = 0; b < B; ++b, ++d) {
+            const int2 ab = rot[b];
+            const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
+                                                uniform_int(ab.y), far, toff, rec, cs, tr, g, sa,
+                                                sp);
+            if (writer) tr_out[d] = (uint16_t)k;
+        }
+    }
+    const float sc = pose_score(Y, n, toff, tr, g);
+    if (writer) ws.rscore[(size_t)l * sa.R + r] = sc;
 }
 
 // Replay restart r of ligand l from its decision trace (same arithmetic as k_dock).
@@ -654,7 +747,7 @@ size_t final_lds_bytes(int nmax, int waves, int R, int K) {
 
 template <int NS>
 __global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
-                                               WorkArgs ws, OutArgs out, int bin) {
+                                               WorkArgs ws, OutArgs out, int bin, int single) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -675,12 +768,20 @@ __global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArg
     int *nsel = rank + K;                     // [1]
     const Tri tr = make_tri(g);
 
-    for (;;) {
-        if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[2 * kNumBins + bin], 1);
-        __syncthreads();
-        const int li = misc[0];
-        if (li >= ws.counters[bin]) break;
-        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+    if (single >= 0 && out.status[single] != 0) return;
+    for (int pass = 0;; ++pass) {
+        int l;
+        if (single >= 0) {
+            // plain form: exactly one ligand, given by the launch
+            if (pass > 0) break;
+            l = single;
+        } else {
+            if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[2 * kNumBins + bin], 1);
+            __syncthreads();
+            const int li = misc[0];
+            if (li >= ws.counters[bin]) break;
+            l = ws.bin_list[(size_t)bin * lib.L + li];
+        }
         stage_ligand<NS>(smem, nmax, l, lib, ws, g, false);
         for (int r = threadIdx.x; r < R; r += blockDim.x) {
             const float s = ws.rscore[(size_t)l * R + r];
@@ -760,7 +861,7 @@ __global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArg
                 Y.z[q] = P[2];
             }
             int o = 0;
-            if (sa.final_align) o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr);
+            if (sa.final_align) o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, WaveSplit());
             const float sc = pose_score(Y, n, toff, tr, g);
             if (lane == 0) {
                 fsc[s] = sc;
@@ -825,9 +926,9 @@ __global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArg
 // bump-pair rows (pairs at least bmin bonds apart), and appends it to its size
 // bin.  A ligand that fails a check gets a status and empty outputs.
 __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                             OutArgs out) {
+                                             OutArgs out, int first, int do_bin) {
     __shared__ u64 adj[kMaxAtoms * 4];   // adjacency + self rows
-    const int l = blockIdx.x;
+    const int l = first + (int)blockIdx.x;
     const int lane = lane_id();
     if (l >= lib.L) return;
     int status = 0;
@@ -942,7 +1043,7 @@ __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs 
                 ws.far[(size_t)(a0 + i) * kFarWords + w] = ~near[w] & valid;
             }
         }
-        if (lane == 0) {
+        if (lane == 0 && do_bin) {
             const int bin = (n - 1) >> 5;
             const int pos = atomicAdd(&ws.counters[bin], 1);
             ws.bin_list[(size_t)bin * lib.L + pos] = l;
@@ -967,6 +1068,16 @@ __global__ void k_reset(int *counters) {
 
 // ---------------------------------------------------------------------------
 // launchers
+hipError_t launch_build_quads(const float *values, float4 *quads, int ntypes, int nx, int ny,
+                              int nz, hipStream_t s) {
+    const long long n = (long long)ntypes * nx * ny * nz;
+    const int threads = 256;
+    const long long blocks = (n + threads - 1) / threads;
+    hipLaunchKernelGGL(k_build_quads, dim3((unsigned)blocks), dim3(threads), 0, s, values, quads,
+                       ntypes, nx, ny, nz);
+    return hipGetLastError();
+}
+
 hipError_t launch_reset(int *counters, hipStream_t s) {
     hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters);
     return hipGetLastError();
@@ -975,8 +1086,49 @@ hipError_t launch_reset(int *counters, hipStream_t s) {
 hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
                        const WorkArgs &ws, const OutArgs &out, hipStream_t s) {
     if (lib.L <= 0) return hipSuccess;
-    hipLaunchKernelGGL(k_prep, dim3(lib.L), dim3(64), 0, s, g, sa, lib, ws, out);
+    hipLaunchKernelGGL(k_prep, dim3(lib.L), dim3(64), 0, s, g, sa, lib, ws, out, 0, 1);
     return hipGetLastError();
+}
+
+hipError_t launch_prep_one(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                           const WorkArgs &ws, const OutArgs &out, int l, hipStream_t s) {
+    hipLaunchKernelGGL(k_prep, dim3(1), dim3(64), 0, s, g, sa, lib, ws, out, l, 0);
+    return hipGetLastError();
+}
+
+size_t plain_lds_bytes(int nmax, int waves) { return dock_lds_bytes(nmax, waves) + (size_t)waves * 8; }
+
+template <int NS, int C>
+static hipError_t launch_plain_t(int l, int bin, int waves, const GridArgs &g,
+                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                 const OutArgs &out, hipStream_t s) {
+    const size_t lds = plain_lds_bytes(bin_nmax(bin), waves);
+    hipFuncSetAttribute((const void *)k_plain<NS, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    hipLaunchKernelGGL((k_plain<NS, C>), dim3(sa.R), dim3(64 * waves), lds, s, g, sa, lib, ws,
+                       (const int *)out.status, l, bin);
+    return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t launch_plain_c(int l, int bin, int waves, const GridArgs &g,
+                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                 const OutArgs &out, hipStream_t s) {
+    const int C = (sa.T + 64 * waves - 1) / (64 * waves);
+    if (C <= 1) return launch_plain_t<NS, 1>(l, bin, waves, g, sa, lib, ws, out, s);
+    if (C <= 2) return launch_plain_t<NS, 2>(l, bin, waves, g, sa, lib, ws, out, s);
+    return launch_plain_t<NS, 4>(l, bin, waves, g, sa, lib, ws, out, s);
+}
+
+hipError_t launch_plain(int l, int bin, int waves, const GridArgs &g, const SearchArgs &sa,
+                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out,
+                        hipStream_t s) {
+    switch (bin_slots(bin)) {
+        case 1: return launch_plain_c<1>(l, bin, waves, g, sa, lib, ws, out, s);
+        case 2: return launch_plain_c<2>(l, bin, waves, g, sa, lib, ws, out, s);
+        case 3: return launch_plain_c<3>(l, bin, waves, g, sa, lib, ws, out, s);
+        default: return launch_plain_c<4>(l, bin, waves, g, sa, lib, ws, out, s);
+    }
 }
 
 template <int NS, int C>
@@ -1015,23 +1167,23 @@ hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const 
 template <int NS>
 static hipError_t launch_final_t(int bin, int blocks, int waves, const GridArgs &g,
                                  const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
-                                 const OutArgs &out, hipStream_t s) {
+                                 const OutArgs &out, int single, hipStream_t s) {
     const size_t lds = final_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K);
     hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     hipLaunchKernelGGL((k_final<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
-                       bin);
+                       bin, single);
     return hipGetLastError();
 }
 
 hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out,
+                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
                         hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_final_t<1>(bin, blocks, waves, g, sa, lib, ws, out, s);
-        case 2: return launch_final_t<2>(bin, blocks, waves, g, sa, lib, ws, out, s);
-        case 3: return launch_final_t<3>(bin, blocks, waves, g, sa, lib, ws, out, s);
-        default: return launch_final_t<4>(bin, blocks, waves, g, sa, lib, ws, out, s);
+        case 1: return launch_final_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 2: return launch_final_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 3: return launch_final_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        default: return launch_final_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
     }
 }
 

@@ -12,12 +12,14 @@ constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 
+// The pocket is kept as corner quads: quad (t,k,j,i) = the grid values at
+// (i,j), (i+1,j), (i,j+1), (i+1,j+1) of slab k of type t (16 bytes), so the 8
+// corners of a trilinear cell are two 16-byte loads (slabs k and k+1).
 struct GridArgs {
-    const float *values;   // [ntypes][nz][ny][nx]
-    uint32_t bytes;        // total bytes of values
-    uint32_t type_bytes;   // nx*ny*nz*4
-    uint32_t row_bytes;    // nx*4
-    uint32_t slab_bytes;   // nx*ny*4
+    const float4 *quads;   // [ntypes][nz][ny][nx] quads
+    uint32_t nquads;       // ntypes*nx*ny*nz
+    uint32_t type_bytes;   // nx*ny*nz*16
+    uint32_t slab_bytes;   // nx*ny*16
     int ntypes, nx, ny, nz;
     float inv_h;
     float ox, oy, oz;      // origin
@@ -75,14 +77,25 @@ size_t dock_lds_bytes(int nmax, int waves);
 size_t final_lds_bytes(int nmax, int waves, int R, int K);
 
 // Launchers (return hipError_t of the launch).
+hipError_t launch_build_quads(const float *values, float4 *quads, int ntypes, int nx, int ny,
+                              int nz, hipStream_t s);
 hipError_t launch_reset(int *counters, hipStream_t s);
 hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
                        const WorkArgs &ws, const OutArgs &out, hipStream_t s);
 hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                        const LibArgs &lib, const WorkArgs &ws, hipStream_t s);
+// single >= 0: only that ligand (plain form), else the bin's queue.
 hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
+                        hipStream_t s);
+// Plain form: checks of ligand l only (no size binning), and its restarts
+// (grid = R workgroups of `waves` waves).
+hipError_t launch_prep_one(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                           const WorkArgs &ws, const OutArgs &out, int l, hipStream_t s);
+hipError_t launch_plain(int l, int bin, int waves, const GridArgs &g, const SearchArgs &sa,
                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out,
                         hipStream_t s);
+size_t plain_lds_bytes(int nmax, int waves);
 // Max resident workgroups per CU for a launch shape (occupancy API).
 int dock_blocks_per_cu(int bin, int waves, int T);
 int final_blocks_per_cu(int bin, int waves, int R, int K);

@@ -43,7 +43,7 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 struct Pocket {
-    float *d_values = nullptr;
+    float4 *d_quads = nullptr;
     GridArgs g{};
     int busy = 0;
 };
@@ -83,11 +83,14 @@ struct dock_ctx {
     std::map<hipStream_t, Workspace> ws;
     std::map<std::string, Tables> tables;
     std::map<std::string, int> occ;
-    hipStream_t submit_stream = nullptr;
+    std::vector<hipStream_t> submit_streams;  // dock_submit: requests round-robin over these
+    size_t next_submit = 0;
     std::map<uint64_t, Ticket> tickets;
     uint64_t next_ticket = 1;
     size_t reserve_bytes = (size_t)1 << 30;
     bool timing = false;
+    std::vector<hipStream_t> plain_streams;  // plain form: ligands round-robin over these
+    std::vector<hipEvent_t> plain_events;
     std::vector<std::array<hipEvent_t, 4>> marks;  // per call: start, after prep, after dock, end
 };
 
@@ -110,7 +113,6 @@ int check_params(const dock_params *p) {
     if (!(p->bump_dist >= 0.f) || !std::isfinite(p->bump_dist)) return fail(DOCK_EINVAL, "bump_dist must be finite and >= 0");
     if (!(p->dedup_rmsd >= 0.f) || !std::isfinite(p->dedup_rmsd)) return fail(DOCK_EINVAL, "dedup_rmsd must be finite and >= 0");
     if (p->mode != DOCK_MODE_BATCHED && p->mode != DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "unknown mode");
-    if (p->mode == DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "plain mode is not available in this build");
     if (!p->start_quat) return fail(DOCK_EINVAL, "start_quat is NULL");
     for (int r = 0; r < p->restarts; ++r) {
         double s = 0;
@@ -261,6 +263,56 @@ int occupancy(dock_ctx *c, const std::string &key, int v) {
 constexpr int kDockWaves = 4;
 constexpr int kFinalWaves = 4;
 
+constexpr int kPlainWaves = 4;
+constexpr int kSubmitStreams = 4;
+constexpr int kPlainStreams = 4;
+
+// Plain (latency) form: one launch sequence per ligand (checks, restarts, select
+// and final step), ligands round-robin over a few streams so that consecutive
+// ligands overlap, as the paper's multi-threaded host does with its streams.
+// The host needs each ligand's size to pick the kernel, so the offsets are read
+// back first (this form is synchronous with respect to the host anyway).
+int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const SearchArgs &sa,
+                  const LibArgs &la, const WorkArgs &wa, const OutArgs &oa,
+                  const std::array<hipEvent_t, 4> &ev, hipStream_t s) {
+    const int L = lib->n_ligands;
+    std::vector<int32_t> ao(L + 1);
+    HIP_TRY(hipMemcpyAsync(ao.data(), lib->atom_off, sizeof(int32_t) * (L + 1),
+                           hipMemcpyDeviceToHost, s));
+    HIP_TRY(hipStreamSynchronize(s));
+    while ((int)c->plain_streams.size() < kPlainStreams) {
+        hipStream_t t;
+        HIP_TRY(hipStreamCreateWithFlags(&t, hipStreamNonBlocking));
+        c->plain_streams.push_back(t);
+        hipEvent_t e;
+        HIP_TRY(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        c->plain_events.push_back(e);
+    }
+    if (c->timing) HIP_TRY(hipEventRecord(ev[0], s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[1], s));
+    hipEvent_t go;
+    HIP_TRY(hipEventCreateWithFlags(&go, hipEventDisableTiming));
+    HIP_TRY(hipEventRecord(go, s));
+    for (auto t : c->plain_streams) HIP_TRY(hipStreamWaitEvent(t, go, 0));
+    for (int l = 0; l < L; ++l) {
+        hipStream_t t = c->plain_streams[l % kPlainStreams];
+        HIP_TRY(launch_prep_one(g, sa, la, wa, oa, l, t));
+        const int n = ao[l + 1] - ao[l];
+        if (n < 1 || n > kMaxAtoms) continue;  // flagged by the checks
+        const int bin = (n - 1) >> 5;
+        HIP_TRY(launch_plain(l, bin, kPlainWaves, g, sa, la, wa, oa, t));
+        HIP_TRY(launch_final(bin, 1, kFinalWaves, g, sa, la, wa, oa, l, t));
+    }
+    for (size_t i = 0; i < c->plain_streams.size(); ++i) {
+        HIP_TRY(hipEventRecord(c->plain_events[i], c->plain_streams[i]));
+        HIP_TRY(hipStreamWaitEvent(s, c->plain_events[i], 0));
+    }
+    HIP_TRY(hipEventDestroy(go));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[2], s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[3], s));
+    return DOCK_OK;
+}
+
 // Enqueue the whole pipeline for a device-resident library.
 int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
                   const dock_results *o, hipStream_t s) {
@@ -331,6 +383,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         c->marks.push_back(ev);
     }
+    if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, g, sa, la, wa, oa, ev, s);
     HIP_TRY(launch_reset(wa.counters, s));
     if (c->timing) HIP_TRY(hipEventRecord(ev[0], s));
     HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
@@ -348,7 +401,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         int blocks = per_cu * c->num_cu;
         if (blocks > la.L) blocks = la.L;
         if (bin == 0 && c->timing) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_final(bin, blocks, kFinalWaves, g, sa, la, wa, oa, s));
+        HIP_TRY(launch_final(bin, blocks, kFinalWaves, g, sa, la, wa, oa, -1, s));
     }
     if (c->timing) HIP_TRY(hipEventRecord(ev[3], s));
     return DOCK_OK;
@@ -375,9 +428,14 @@ int dock_create(int device, dock_ctx **out) {
     if (!c) return fail(DOCK_ENOMEM, "context allocation failed");
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
-    if (hipStreamCreateWithFlags(&c->submit_stream, hipStreamNonBlocking) != hipSuccess) {
-        delete c;
-        return fail(DOCK_EDEVICE, "stream creation failed");
+    for (int i = 0; i < kSubmitStreams; ++i) {
+        hipStream_t t = nullptr;
+        if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
+            for (auto u : c->submit_streams) (void)hipStreamDestroy(u);
+            delete c;
+            return fail(DOCK_EDEVICE, "stream creation failed");
+        }
+        c->submit_streams.push_back(t);
     }
     *out = c;
     g_err.clear();
@@ -392,12 +450,14 @@ int dock_destroy(dock_ctx *c) {
         if (kv.second.done) hipEventDestroy(kv.second.done);
         if (kv.second.host_stage) hipHostFree(kv.second.host_stage);
     }
-    for (auto &kv : c->pockets) hipFree(kv.second.d_values);
+    for (auto &kv : c->pockets) hipFree(kv.second.d_quads);
     for (auto &kv : c->ws) hipFree(kv.second.base);
     for (auto &kv : c->tables) hipFree(kv.second.d);
     for (auto &m : c->marks)
         for (auto &e : m) hipEventDestroy(e);
-    if (c->submit_stream) hipStreamDestroy(c->submit_stream);
+    for (auto t : c->submit_streams) hipStreamDestroy(t);
+    for (auto t : c->plain_streams) hipStreamDestroy(t);
+    for (auto e : c->plain_events) hipEventDestroy(e);
     delete c;
     return DOCK_OK;
 }
@@ -409,7 +469,8 @@ int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) 
     const long long cells = (long long)gd->nx * gd->ny * gd->nz;
     if (cells >= (1LL << 24)) return fail(DOCK_EINVAL, "nx*ny*nz must be < 2^24");
     const long long bytes = cells * 4 * gd->ntypes;
-    if (bytes >= (1LL << 32)) return fail(DOCK_EINVAL, "grid larger than 4 GiB");
+    const long long qbytes = cells * 16 * gd->ntypes;
+    if (qbytes >= (1LL << 32)) return fail(DOCK_EINVAL, "grid too large (ntypes*nx*ny*nz*16 >= 4 GiB)");
     if (!(gd->spacing > 0.f) || !std::isfinite(gd->spacing)) return fail(DOCK_EINVAL, "spacing must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(gd->origin[a])) return fail(DOCK_EINVAL, "origin must be finite");
@@ -417,20 +478,29 @@ int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) 
     std::lock_guard<std::mutex> lk(c->mu);
     HIP_TRY(hipSetDevice(c->device));
     Pocket pk;
-    if (hipMalloc(&pk.d_values, (size_t)bytes) != hipSuccess) {
+    float *d_vals = nullptr;
+    if (hipMalloc(&d_vals, (size_t)bytes) != hipSuccess) {
         (void)hipGetLastError();
+        return fail(DOCK_ENOMEM, "pocket staging allocation failed");
+    }
+    if (hipMalloc(&pk.d_quads, (size_t)qbytes) != hipSuccess) {
+        (void)hipGetLastError();
+        hipFree(d_vals);
         return fail(DOCK_ENOMEM, "pocket allocation failed");
     }
-    if (hipMemcpy(pk.d_values, gd->values, (size_t)bytes, hipMemcpyHostToDevice) != hipSuccess) {
-        hipFree(pk.d_values);
-        return fail(DOCK_EDEVICE, "pocket copy failed");
+    hipError_t e = hipMemcpy(d_vals, gd->values, (size_t)bytes, hipMemcpyHostToDevice);
+    if (!e) e = launch_build_quads(d_vals, pk.d_quads, gd->ntypes, gd->nx, gd->ny, gd->nz, nullptr);
+    if (!e) e = hipDeviceSynchronize();
+    hipFree(d_vals);
+    if (e) {
+        hipFree(pk.d_quads);
+        return fail(DOCK_EDEVICE, std::string("pocket upload failed: ") + hipGetErrorString(e));
     }
     GridArgs &g = pk.g;
-    g.values = pk.d_values;
-    g.bytes = (uint32_t)bytes;
-    g.type_bytes = (uint32_t)(cells * 4);
-    g.row_bytes = (uint32_t)gd->nx * 4;
-    g.slab_bytes = (uint32_t)gd->nx * gd->ny * 4;
+    g.quads = pk.d_quads;
+    g.nquads = (uint32_t)(cells * gd->ntypes);
+    g.type_bytes = (uint32_t)(cells * 16);
+    g.slab_bytes = (uint32_t)((long long)gd->nx * gd->ny * 16);
     g.ntypes = gd->ntypes;
     g.nx = gd->nx;
     g.ny = gd->ny;
@@ -464,7 +534,7 @@ int dock_pocket_unload(dock_ctx *c, int32_t pocket_id) {
     if (it->second.busy) return fail(DOCK_EBUSY, "pocket has submitted work in flight");
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    hipFree(it->second.d_values);
+    hipFree(it->second.d_quads);
     c->pockets.erase(it);
     return DOCK_OK;
 }
@@ -527,15 +597,18 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     t.stage_bytes = so;
     const size_t dev_bytes = off + so;
     // admission: library + results + workspace must fit in free memory less a reserve
+    hipStream_t s_pick = nullptr;
     {
         const WsLayout wl = ws_layout(lib, p, o->trace != nullptr);
         size_t freeb = 0, totalb = 0;
         HIP_TRY(hipMemGetInfo(&freeb, &totalb));
-        const size_t have_ws = c->ws.count(c->submit_stream) ? c->ws[c->submit_stream].bytes : 0;
+        s_pick = c->submit_streams[c->next_submit % c->submit_streams.size()];
+        const size_t have_ws = c->ws.count(s_pick) ? c->ws[s_pick].bytes : 0;
         const size_t need = dev_bytes + (wl.total > have_ws ? wl.total : 0);
         if (need + c->reserve_bytes > freeb) return fail(DOCK_EAGAIN, "not enough free device memory");
     }
-    hipStream_t s = c->submit_stream;
+    hipStream_t s = s_pick;
+    c->next_submit += 1;
     char *d = nullptr;
     if (hipMallocAsync((void **)&d, dev_bytes > 0 ? dev_bytes : 256, s) != hipSuccess) {
         (void)hipGetLastError();

@@ -197,3 +197,34 @@ def test_config2_full_size_sampled(D, ctx):
     rng = np.random.default_rng(2209)
     sample = sorted(int(v) for v in rng.choice(L, 3, replace=False))
     check_all(D, pk, lib, q, h, params, ligands=sample, label="c2-sample")
+
+
+def test_plain_form_matches_batched_form_bitwise(D, ctx):
+    """The plain (latency) form makes the same decisions with the same arithmetic
+    as the batched form; its outputs must be identical, and pass parity."""
+    for label, (pk, lib, q, s) in (
+            ("c1", synth.config(1)),
+            ("ragged", (synth.pocket_gaussians(302, 4, 48, 0.5, 60, 6.0),
+                        synth.library_from_sizes(302, [3, 20, 33, 64, 65, 100, 150, 256],
+                                                 [0, 3, 5, 8, 4, 12, 20, 24]),
+                        synth.start_quats(302, 6),
+                        dict(torsion_steps=100, sweep_passes=2, align_steps=7, top_k=8,
+                             dedup_rmsd=1.0)))):
+        print(f"[case] plain vs batched {label}", flush=True)
+        hb, params = run_batch(D, ctx, pk, lib, q, **s)
+        hp, pparams = run_batch(D, ctx, pk, lib, q, mode=D.DOCK_MODE_PLAIN, **s)
+        for k in hb:
+            if hb[k] is not None:
+                np.testing.assert_array_equal(hb[k], hp[k], err_msg=f"{label}:{k}")
+        check_all(D, pk, lib, q, hp, pparams, label=f"plain-{label}")
+
+
+def test_plain_form_flags_invalid_ligands(D, ctx):
+    lib = synth.library_uniform(331, 6, (15, 30), (2, 4))
+    pk = synth.pocket_gaussians(331, 4, 32, 0.5, 40, 4.0)
+    q = synth.start_quats(331, 4)
+    bad = _corrupt(lib)
+    h, params = run_batch(D, ctx, pk, bad, q, torsion_steps=32, sweep_passes=1, align_steps=6,
+                          top_k=4, mode=D.DOCK_MODE_PLAIN)
+    assert list(h["status"]) == [0, 2, 4, 3, 0, 0]
+    check_all(D, pk, bad, q, h, params, ligands=[0, 4, 5], label="plain-valid-in-bad-batch")
