@@ -46,10 +46,31 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=8.0)
     ap.add_argument("--serve-loads", type=str, default="0.5,0.8",
                     help="offered load as fractions of the measured batched saturation")
+    ap.add_argument("--sweep", action="store_true",
+                    help="size grid and library-size sweep, plain vs batched (config 4)")
+    ap.add_argument("--sweep-ligands", type=int, default=20000,
+                    help="ligands per size-grid cell (batched form)")
+    ap.add_argument("--sweep-plain-ligands", type=int, default=2000,
+                    help="ligands per size-grid cell timed in the plain form")
+    ap.add_argument("--sweep-library", type=str, default="100,1000,10000,100000,1000000")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference kernel "
                          "for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+def describe(cfg, L, s):
+    import synth
+    c = synth.CONFIGS[cfg]
+    pk, lg = c["pocket"], c["ligands"]
+    names = {1: "small plain workload", 2: "paper-scale plain workload",
+             3: "large batched workload"}
+    return (f"{names.get(cfg, 'workload')} (config {cfg}): {L} random-tree ligands (heavy atoms "
+            f"U{{{lg['atoms'][0]}..{lg['atoms'][1]}}}, rotatable bonds U{{{lg['rot'][0]}.."
+            f"{lg['rot'][1]}}}), {pk['ntypes']}-type {pk['n']}^3 pocket at {pk['spacing']} A; "
+            f"R={s['restarts']} restarts, T={s['torsion_steps']} torsion steps, "
+            f"P={s['sweep_passes']} passes, {s['align_steps']}x{s['align_steps']} alignment, "
+            f"top-{s['top_k']} with {s['dedup_rmsd']} A dedup")
 
 
 def workload_counts(lib, s):
@@ -154,6 +175,77 @@ def serve_main(a):
     print(json.dumps(out), flush=True)
 
 
+def _time_call(D, torch, ctx, pid, lib, params, reps=1):
+    dl = D.DeviceLibrary(lib)
+    res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params)
+    D.dock_ligands_batch(ctx, pid, dl, params, res)      # warm (workspace, tables)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(reps):
+        D.dock_ligands_batch(ctx, pid, dl, params, res)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / reps
+    del dl, res
+    return lib.n_ligands / (ms * 1e-3)
+
+
+def sweep_main(a):
+    """Size grid (heavy atoms {16,32,64,128} x rotatable bonds {0,4,8,16,24}) and
+    library-size sweep (40 atoms / 8 bonds), plain vs batched, R=128 restarts,
+    T=256 steps, P=3, K=30, on the paper-scale pocket.  The plain form is timed on
+    the first --sweep-plain-ligands ligands of each library (its throughput does
+    not depend on library size beyond a few launches per stream)."""
+    import torch
+    import synth
+    from paper_2209_05069_amd import dock as D
+    seed = synth.MASTER_SEED + 4
+    c2 = synth.CONFIGS[2]
+    pk = synth.pocket_gaussians(seed, **c2["pocket"])
+    s = dict(c2["search"])
+    s["restarts"] = 128
+    q = synth.start_quats(seed, 128)
+    ctx = D.dock_create(0)
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    pb = D.SearchParams(q, **s)
+    pp = D.SearchParams(q, mode=D.DOCK_MODE_PLAIN, **s)
+    cells = []
+    for n in (16, 32, 64, 128):
+        for B in (0, 4, 8, 16, 24):
+            if B > max(n - 3, 0):
+                cells.append(dict(atoms=n, bonds=B, feasible=False))
+                print(f"[sweep] {n} atoms x {B} bonds: infeasible (a tree of {n} atoms has at "
+                      f"most {n - 3} non-terminal edges)", file=sys.stderr, flush=True)
+                continue
+            L = a.sweep_ligands
+            lib = synth.library_from_sizes(seed + 1000 * n + B, np.full(L, n, np.int32),
+                                           np.full(L, B, np.int32))
+            clipped = int((lib.n_rot() < B).sum())
+            bat = _time_call(D, torch, ctx, pid, lib, pb)
+            sub = lib.subset(range(min(L, a.sweep_plain_ligands)))
+            pla = _time_call(D, torch, ctx, pid, sub, pp)
+            cells.append(dict(atoms=n, bonds=B, feasible=True, ligands=L, clipped=clipped,
+                              batched_ligands_per_s=bat, plain_ligands_per_s=pla,
+                              batched_over_plain=bat / pla))
+            print(f"[sweep] {n} atoms x {B} bonds: batched {bat:.0f}/s, plain {pla:.0f}/s, "
+                  f"x{bat / pla:.2f} (clipped {clipped})", file=sys.stderr, flush=True)
+    lib_runs = []
+    sizes = [int(x) for x in a.sweep_library.split(",")]
+    big = synth.library_from_sizes(seed + 7, np.full(max(sizes), 40, np.int32),
+                                   np.full(max(sizes), 8, np.int32))
+    for L in sizes:
+        lib = big.subset(range(L)) if L < big.n_ligands else big
+        bat = _time_call(D, torch, ctx, pid, lib, pb)
+        pla = _time_call(D, torch, ctx, pid, lib.subset(range(min(L, a.sweep_plain_ligands))), pp)
+        lib_runs.append(dict(ligands=L, batched_ligands_per_s=bat, plain_ligands_per_s=pla))
+        print(f"[sweep] library {L}: batched {bat:.0f}/s, plain {pla:.0f}/s", file=sys.stderr,
+              flush=True)
+    D.dock_destroy(ctx)
+    print(json.dumps({"sweep": "size grid and library size (config 4)", "search": s,
+                      "cells": cells, "library": lib_runs}), flush=True)
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -163,6 +255,8 @@ def main():
         sys.exit(2)
     if a.serve:
         return serve_main(a)
+    if a.sweep:
+        return sweep_main(a)
     import torch
     import synth
     from paper_2209_05069_amd import dock as D
@@ -235,11 +329,7 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": (f"paper-scale plain workload (config {a.config}): {L} random-tree ligands "
-                         f"(heavy atoms U{{20..80}}, rotatable bonds U{{2..12}}), 4-type 96^3 "
-                         f"pocket at 0.375 A; R={s['restarts']} restarts, T={s['torsion_steps']} "
-                         f"torsion steps, P={s['sweep_passes']} passes, 30x30 alignment, "
-                         f"top-{s['top_k']} with {s['dedup_rmsd']} A dedup"),
+            "workload": describe(a.config, L, s),
             "form": "batched (persistent wavefront-per-restart kernels, size-binned)",
             "ligands": L,
         },

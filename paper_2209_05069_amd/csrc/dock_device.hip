@@ -19,8 +19,10 @@
 //    remaining pairs against every candidate with two FMAs; one 64-bit key max
 //    (order-preserving score bits, then the lower index) over the bump-free
 //    candidates picks the step;
-//  * grid gathers are raw buffer loads: one 32-bit voffset for the cell and the
-//    8 corners as scalar offsets, with the range checked by hardware;
+//  * grid gathers are raw buffer loads of corner cubes (the 8 corner values of
+//    a cell in one 32-byte record): two 16-byte loads from one cache line per
+//    sample, a 32-bit voffset for the cell and the atom type as scalar offset,
+//    with the range checked by hardware;
 //  * a persistent grid pops (ligand, restart-group) items from a per-bin queue;
 //    the ligand's coordinates, bump-pair rows and masks are staged once per
 //    item in LDS and shared by the workgroup's waves.
@@ -89,29 +91,27 @@ __device__ __forceinline__ void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 // Trilinear interpolation.  (gx,gy,gz) are grid coordinates ((p - origin)/h);
 // each is clamped to [0, n-1], the cell corner is min(floor, n-2).  The pocket
-// is stored as corner quads (see GridArgs), so the 8 corners are two 16-byte
-// loads: the quad of slab k and the quad of slab k+1 (scalar offset slab_bytes).
+// is stored as corner cubes (see GridArgs): the 8 corners of a cell are one
+// 32-byte record, read as two 16-byte loads from the same cache line.
 // toff is the byte offset of the atom type's block.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 struct Tri {
     __amdgpu_buffer_rsrc_t rs;
-    uint32_t slab;
     float mx, my, mz, m2x, m2y, m2z, fnx, fslab;
 };
 
 __device__ __forceinline__ Tri make_tri(const GridArgs &g) {
     Tri t;
-    t.rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.quads, (short)0,
-                                             (int)(g.nquads * 16u), 0x00020000);
-    t.slab = g.slab_bytes;
+    t.rs = __builtin_amdgcn_make_buffer_rsrc((void *)g.cubes, (short)0,
+                                             (int)(g.ncells * 32u), 0x00020000);
     t.mx = g.mx; t.my = g.my; t.mz = g.mz;
     t.m2x = g.m2x; t.m2y = g.m2y; t.m2z = g.m2z;
     t.fnx = g.fnx; t.fslab = g.fslab;
     return t;
 }
 
-// byte offset of the cell's quad within the type block, and the fractions
+// byte offset of the cell record within the type block, and the fractions
 __device__ __forceinline__ uint32_t tri_cell(const Tri &t, float gx, float gy, float gz, float &fx,
                                              float &fy, float &fz) {
     const float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
@@ -125,7 +125,7 @@ __device__ __forceinline__ uint32_t tri_cell(const Tri &t, float gx, float gy, f
     fz = cz - iz;
     // element index < 2^24: exact in float
     const float e = fmaf(iz, t.fslab, fmaf(iy, t.fnx, ix));
-    return ((uint32_t)e) << 4;
+    return ((uint32_t)e) << 5;
 }
 
 // 16-byte raw buffer load; the builtin returns the bits as integers.
@@ -152,7 +152,7 @@ __device__ __forceinline__ float tri_u(const Tri &t, float gx, float gy, float g
     float fx, fy, fz;
     const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz);
     const float4 q0 = ldq(t.rs, off, toff);
-    const float4 q1 = ldq(t.rs, off, toff + (int)t.slab);
+    const float4 q1 = ldq(t.rs, off, toff + 16);
     return tri_blend(q0, q1, fx, fy, fz);
 }
 
@@ -161,13 +161,14 @@ __device__ __forceinline__ float tri_v(const Tri &t, float gx, float gy, float g
     float fx, fy, fz;
     const uint32_t off = tri_cell(t, gx, gy, gz, fx, fy, fz) + toff;
     const float4 q0 = ldq(t.rs, off, 0);
-    const float4 q1 = ldq(t.rs, off, (int)t.slab);
+    const float4 q1 = ldq(t.rs, off, 16);
     return tri_blend(q0, q1, fx, fy, fz);
 }
 
-// Corner quads from the plain grid (one thread per quad).  Quads at i = nx-1 or
-// j = ny-1 are never read (the cell corner is at most n-2); they repeat the edge.
-__global__ void k_build_quads(const float *__restrict__ v, float4 *__restrict__ q, int ntypes,
+// Corner cubes from the plain grid (one thread per cell).  Cells at i = nx-1,
+// j = ny-1 or k = nz-1 are never read (the cell corner is at most n-2); they
+// repeat the edge values.
+__global__ void k_build_cubes(const float *__restrict__ v, float4 *__restrict__ q, int ntypes,
                               int nx, int ny, int nz) {
     const long long cells = (long long)nx * ny * nz;
     const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
@@ -177,10 +178,13 @@ __global__ void k_build_quads(const float *__restrict__ v, float4 *__restrict__ 
     const int k = (int)(r / ((long long)nx * ny));
     r -= (long long)k * nx * ny;
     const int j = (int)(r / nx), i = (int)(r - (long long)j * nx);
-    const int i1 = i + 1 < nx ? i + 1 : i, j1 = j + 1 < ny ? j + 1 : j;
-    const float *b = v + t * cells + (long long)k * nx * ny;
-    q[e] = make_float4(b[(long long)j * nx + i], b[(long long)j * nx + i1],
-                       b[(long long)j1 * nx + i], b[(long long)j1 * nx + i1]);
+    const int i1 = i + 1 < nx ? i + 1 : i, j1 = j + 1 < ny ? j + 1 : j, k1 = k + 1 < nz ? k + 1 : k;
+    const float *b0 = v + t * cells + (long long)k * nx * ny;
+    const float *b1 = v + t * cells + (long long)k1 * nx * ny;
+    q[2 * e] = make_float4(b0[(long long)j * nx + i], b0[(long long)j * nx + i1],
+                           b0[(long long)j1 * nx + i], b0[(long long)j1 * nx + i1]);
+    q[2 * e + 1] = make_float4(b1[(long long)j * nx + i], b1[(long long)j * nx + i1],
+                               b1[(long long)j1 * nx + i], b1[(long long)j1 * nx + i1]);
 }
 
 // ---------------------------------------------------------------------------
@@ -1068,12 +1072,12 @@ __global__ void k_reset(int *counters) {
 
 // ---------------------------------------------------------------------------
 // launchers
-hipError_t launch_build_quads(const float *values, float4 *quads, int ntypes, int nx, int ny,
+hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, int nx, int ny,
                               int nz, hipStream_t s) {
     const long long n = (long long)ntypes * nx * ny * nz;
     const int threads = 256;
     const long long blocks = (n + threads - 1) / threads;
-    hipLaunchKernelGGL(k_build_quads, dim3((unsigned)blocks), dim3(threads), 0, s, values, quads,
+    hipLaunchKernelGGL(k_build_cubes, dim3((unsigned)blocks), dim3(threads), 0, s, values, cubes,
                        ntypes, nx, ny, nz);
     return hipGetLastError();
 }

@@ -12,14 +12,13 @@ constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 
-// The pocket is kept as corner quads: quad (t,k,j,i) = the grid values at
-// (i,j), (i+1,j), (i,j+1), (i+1,j+1) of slab k of type t (16 bytes), so the 8
-// corners of a trilinear cell are two 16-byte loads (slabs k and k+1).
+// The pocket is kept as corner cubes: cube (t,k,j,i) = the grid values of type
+// t at (i,j,k), (i+1,j,k), (i,j+1,k), (i+1,j+1,k), then the same four of slab
+// k+1 (32 bytes), so the 8 corners of a trilinear cell sit in one cache line.
 struct GridArgs {
-    const float4 *quads;   // [ntypes][nz][ny][nx] quads
-    uint32_t nquads;       // ntypes*nx*ny*nz
-    uint32_t type_bytes;   // nx*ny*nz*16
-    uint32_t slab_bytes;   // nx*ny*16
+    const float4 *cubes;   // [ntypes][nz][ny][nx] cubes, 2 float4 each
+    uint32_t ncells;       // ntypes*nx*ny*nz
+    uint32_t type_bytes;   // nx*ny*nz*32
     int ntypes, nx, ny, nz;
     float inv_h;
     float ox, oy, oz;      // origin
@@ -77,7 +76,7 @@ size_t dock_lds_bytes(int nmax, int waves);
 size_t final_lds_bytes(int nmax, int waves, int R, int K);
 
 // Launchers (return hipError_t of the launch).
-hipError_t launch_build_quads(const float *values, float4 *quads, int ntypes, int nx, int ny,
+hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, int nx, int ny,
                               int nz, hipStream_t s);
 hipError_t launch_reset(int *counters, hipStream_t s);
 hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,

@@ -43,7 +43,7 @@ int fail(int code, const std::string &msg) {
     } while (0)
 
 struct Pocket {
-    float4 *d_quads = nullptr;
+    float4 *d_cubes = nullptr;
     GridArgs g{};
     int busy = 0;
 };
@@ -89,6 +89,10 @@ struct dock_ctx {
     uint64_t next_ticket = 1;
     size_t reserve_bytes = (size_t)1 << 30;
     bool timing = false;
+    // Batched launch sequences seen once (eager) and captured as graphs when they
+    // repeat with identical arguments.
+    std::map<std::string, int> seen_keys;
+    std::map<std::string, hipGraphExec_t> graphs;
     std::vector<hipStream_t> plain_streams;  // plain form: ligands round-robin over these
     std::vector<hipEvent_t> plain_events;
     std::vector<std::array<hipEvent_t, 4>> marks;  // per call: start, after prep, after dock, end
@@ -384,26 +388,64 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         c->marks.push_back(ev);
     }
     if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, g, sa, la, wa, oa, ev, s);
-    HIP_TRY(launch_reset(wa.counters, s));
-    if (c->timing) HIP_TRY(hipEventRecord(ev[0], s));
-    HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
-    if (c->timing) HIP_TRY(hipEventRecord(ev[1], s));
+    // launch shapes (occupancy queries stay outside any graph capture)
+    int dock_blocks[kNumBins], final_blocks[kNumBins];
     for (int bin = 0; bin < kNumBins; ++bin) {
         const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(kDockWaves) + "/" +
                               std::to_string((sa.T + 63) / 64);
-        const int per_cu = occupancy(c, k, dock_blocks_per_cu(bin, kDockWaves, sa.T));
-        HIP_TRY(launch_dock(bin, per_cu * c->num_cu, kDockWaves, g, sa, la, wa, s));
-    }
-    for (int bin = 0; bin < kNumBins; ++bin) {
-        const std::string k = "f" + std::to_string(bin) + "/" + std::to_string(kFinalWaves) + "/" +
+        dock_blocks[bin] = occupancy(c, k, dock_blocks_per_cu(bin, kDockWaves, sa.T)) * c->num_cu;
+        const std::string f = "f" + std::to_string(bin) + "/" + std::to_string(kFinalWaves) + "/" +
                               std::to_string(sa.R) + "/" + std::to_string(sa.K);
-        const int per_cu = occupancy(c, k, final_blocks_per_cu(bin, kFinalWaves, sa.R, sa.K));
-        int blocks = per_cu * c->num_cu;
-        if (blocks > la.L) blocks = la.L;
-        if (bin == 0 && c->timing) HIP_TRY(hipEventRecord(ev[2], s));
-        HIP_TRY(launch_final(bin, blocks, kFinalWaves, g, sa, la, wa, oa, -1, s));
+        int blocks = occupancy(c, f, final_blocks_per_cu(bin, kFinalWaves, sa.R, sa.K)) * c->num_cu;
+        final_blocks[bin] = blocks > la.L ? la.L : blocks;
     }
-    if (c->timing) HIP_TRY(hipEventRecord(ev[3], s));
+    auto sequence = [&](bool marks) -> int {
+        HIP_TRY(launch_reset(wa.counters, s));
+        if (marks) HIP_TRY(hipEventRecord(ev[0], s));
+        HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
+        if (marks) HIP_TRY(hipEventRecord(ev[1], s));
+        for (int bin = 0; bin < kNumBins; ++bin)
+            HIP_TRY(launch_dock(bin, dock_blocks[bin], kDockWaves, g, sa, la, wa, s));
+        if (marks) HIP_TRY(hipEventRecord(ev[2], s));
+        for (int bin = 0; bin < kNumBins; ++bin)
+            HIP_TRY(launch_final(bin, final_blocks[bin], kFinalWaves, g, sa, la, wa, oa, -1, s));
+        if (marks) HIP_TRY(hipEventRecord(ev[3], s));
+        return DOCK_OK;
+    };
+    if (c->timing || s == nullptr) return sequence(c->timing);
+    // graph key: everything the kernels' arguments depend on
+    std::string key((const char *)&g, sizeof(g));
+    key.append((const char *)&sa, sizeof(sa));
+    key.append((const char *)&la, sizeof(la));
+    key.append((const char *)&wa, sizeof(wa));
+    key.append((const char *)&oa, sizeof(oa));
+    key.append((const char *)&s, sizeof(s));
+    auto gi = c->graphs.find(key);
+    if (gi == c->graphs.end()) {
+        if (c->seen_keys[key]++ == 0) {
+            if (c->seen_keys.size() > 256) c->seen_keys.clear();
+            return sequence(false);  // first time: eager
+        }
+        if (c->graphs.size() >= 16) {
+            for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
+            c->graphs.clear();
+        }
+        hipGraph_t graph = nullptr;
+        HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
+        const int rc2 = sequence(false);
+        const hipError_t ec = hipStreamEndCapture(s, &graph);
+        if (rc2) {
+            if (graph) (void)hipGraphDestroy(graph);
+            return rc2;
+        }
+        if (ec != hipSuccess) return fail(DOCK_EDEVICE, std::string("graph capture: ") + hipGetErrorString(ec));
+        hipGraphExec_t exec = nullptr;
+        const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (ei != hipSuccess) return fail(DOCK_EDEVICE, std::string("graph instantiate: ") + hipGetErrorString(ei));
+        gi = c->graphs.emplace(key, exec).first;
+    }
+    HIP_TRY(hipGraphLaunch(gi->second, s));
     return DOCK_OK;
 }
 
@@ -450,11 +492,12 @@ int dock_destroy(dock_ctx *c) {
         if (kv.second.done) hipEventDestroy(kv.second.done);
         if (kv.second.host_stage) hipHostFree(kv.second.host_stage);
     }
-    for (auto &kv : c->pockets) hipFree(kv.second.d_quads);
+    for (auto &kv : c->pockets) hipFree(kv.second.d_cubes);
     for (auto &kv : c->ws) hipFree(kv.second.base);
     for (auto &kv : c->tables) hipFree(kv.second.d);
     for (auto &m : c->marks)
         for (auto &e : m) hipEventDestroy(e);
+    for (auto &kv : c->graphs) hipGraphExecDestroy(kv.second);
     for (auto t : c->submit_streams) hipStreamDestroy(t);
     for (auto t : c->plain_streams) hipStreamDestroy(t);
     for (auto e : c->plain_events) hipEventDestroy(e);
@@ -469,8 +512,8 @@ int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) 
     const long long cells = (long long)gd->nx * gd->ny * gd->nz;
     if (cells >= (1LL << 24)) return fail(DOCK_EINVAL, "nx*ny*nz must be < 2^24");
     const long long bytes = cells * 4 * gd->ntypes;
-    const long long qbytes = cells * 16 * gd->ntypes;
-    if (qbytes >= (1LL << 32)) return fail(DOCK_EINVAL, "grid too large (ntypes*nx*ny*nz*16 >= 4 GiB)");
+    const long long qbytes = cells * 32 * gd->ntypes;
+    if (qbytes >= (1LL << 32)) return fail(DOCK_EINVAL, "grid too large (ntypes*nx*ny*nz*32 >= 4 GiB)");
     if (!(gd->spacing > 0.f) || !std::isfinite(gd->spacing)) return fail(DOCK_EINVAL, "spacing must be > 0");
     for (int a = 0; a < 3; ++a)
         if (!std::isfinite(gd->origin[a])) return fail(DOCK_EINVAL, "origin must be finite");
@@ -483,24 +526,23 @@ int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) 
         (void)hipGetLastError();
         return fail(DOCK_ENOMEM, "pocket staging allocation failed");
     }
-    if (hipMalloc(&pk.d_quads, (size_t)qbytes) != hipSuccess) {
+    if (hipMalloc(&pk.d_cubes, (size_t)qbytes) != hipSuccess) {
         (void)hipGetLastError();
         hipFree(d_vals);
         return fail(DOCK_ENOMEM, "pocket allocation failed");
     }
     hipError_t e = hipMemcpy(d_vals, gd->values, (size_t)bytes, hipMemcpyHostToDevice);
-    if (!e) e = launch_build_quads(d_vals, pk.d_quads, gd->ntypes, gd->nx, gd->ny, gd->nz, nullptr);
+    if (!e) e = launch_build_cubes(d_vals, pk.d_cubes, gd->ntypes, gd->nx, gd->ny, gd->nz, nullptr);
     if (!e) e = hipDeviceSynchronize();
     hipFree(d_vals);
     if (e) {
-        hipFree(pk.d_quads);
+        hipFree(pk.d_cubes);
         return fail(DOCK_EDEVICE, std::string("pocket upload failed: ") + hipGetErrorString(e));
     }
     GridArgs &g = pk.g;
-    g.quads = pk.d_quads;
-    g.nquads = (uint32_t)(cells * gd->ntypes);
-    g.type_bytes = (uint32_t)(cells * 16);
-    g.slab_bytes = (uint32_t)((long long)gd->nx * gd->ny * 16);
+    g.cubes = pk.d_cubes;
+    g.ncells = (uint32_t)(cells * gd->ntypes);
+    g.type_bytes = (uint32_t)(cells * 32);
     g.ntypes = gd->ntypes;
     g.nx = gd->nx;
     g.ny = gd->ny;
@@ -534,7 +576,7 @@ int dock_pocket_unload(dock_ctx *c, int32_t pocket_id) {
     if (it->second.busy) return fail(DOCK_EBUSY, "pocket has submitted work in flight");
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    hipFree(it->second.d_quads);
+    hipFree(it->second.d_cubes);
     c->pockets.erase(it);
     return DOCK_OK;
 }

@@ -228,3 +228,35 @@ def test_plain_form_flags_invalid_ligands(D, ctx):
                           top_k=4, mode=D.DOCK_MODE_PLAIN)
     assert list(h["status"]) == [0, 2, 4, 3, 0, 0]
     check_all(D, pk, bad, q, h, params, ligands=[0, 4, 5], label="plain-valid-in-bad-batch")
+
+
+def test_graph_replays_match_eager(D, ctx):
+    """Repeated identical calls are captured as a graph and replayed; every replay,
+    with other eager work and synchronisations between replays, must equal the
+    first (eager) result bit for bit."""
+    pk, lib, q, s = synth.config(1)
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    params = D.SearchParams(q, **s)
+    dl = D.DeviceLibrary(lib)
+    res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params,
+                          restart_scores=True, trace=True, final_trace=True)
+    other = synth.library_uniform(360, 5, (15, 40), (1, 5))
+    do = D.DeviceLibrary(other)
+    ro = D.DeviceResults(other.n_ligands, do.n_atoms_total, do.n_rot_total, params)
+    st = torch.cuda.Stream()
+    D.dock_ligands_batch(ctx, pid, dl, params, res, st)        # first call: eager
+    st.synchronize()
+    eager = res.to_host()
+    for rep in range(4):                                        # capture, then replays
+        with torch.cuda.stream(st):
+            for t in (res.best_score, res.pose_score, res.pose_xyz, res.restart_score):
+                t.fill_(float("nan"))
+        D.dock_ligands_batch(ctx, pid, dl, params, res, st)
+        st.synchronize()
+        got = res.to_host()
+        for k in eager:
+            if eager[k] is not None:
+                np.testing.assert_array_equal(eager[k], got[k], err_msg=f"replay {rep}: {k}")
+        D.dock_ligands_batch(ctx, pid, do, params, ro)          # other eager work between
+        torch.cuda.synchronize()
+    D.dock_pocket_unload(ctx, pid)
