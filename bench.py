@@ -29,6 +29,13 @@ sys.path.insert(0, ROOT)
 FLOP_PER_SAMPLE = 49
 PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 
+# HBM bytes of the docking kernels per step of the default workload, from two
+# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
+# plain 256 MiB copy read in the same program).  Valid only for the kernel
+# source they were taken on (sha256 prefix below); reported as null otherwise.
+TRAFFIC_SOURCE_SHA = "bc4aeed7d766c5ff"
+TRAFFIC_BYTES_PER_STEP = 8.848679e+11
+
 
 def parse():
     ap = argparse.ArgumentParser()
@@ -57,6 +64,16 @@ def parse():
                     help="run one plain device copy of this size first (reference kernel "
                          "for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+def kernel_traffic(cfg, L):
+    import hashlib
+    src = os.path.join(ROOT, "paper_2209_05069_amd", "csrc", "dock_device.hip")
+    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    import synth
+    if sha == TRAFFIC_SOURCE_SHA and cfg == 2 and L == synth.CONFIGS[2]["ligands"]["L"]:
+        return TRAFFIC_BYTES_PER_STEP
+    return None
 
 
 def describe(cfg, L, s):
@@ -345,7 +362,8 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": None,
+            "traffic": kernel_traffic(a.config, L),
+            "traffic_unit": "bytes per step (docking kernels, HBM side of L2)",
             "kernel": "k_dock (all size bins of one step)",
             "flop_per_step": samples * FLOP_PER_SAMPLE,
             "atom_samples_per_step": samples,
