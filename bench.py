@@ -164,7 +164,7 @@ def serve_main(a):
     runs = []
     for load in [float(x) for x in a.serve_loads.split(",")]:
         qps = load * sat
-        n = int(qps * a.serve_seconds)
+        n = min(int(qps * a.serve_seconds), 2_000_000)
         lib = synth.library_lognormal(seed + 7, n)
         rng = np.random.default_rng(seed + int(1000 * load))
         reqs = [S.Request(i, int(rng.integers(0, 8)), i, 0.0) for i in range(n)]

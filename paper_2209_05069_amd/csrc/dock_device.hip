@@ -750,7 +750,7 @@ size_t final_lds_bytes(int nmax, int waves, int R, int K) {
 }
 
 template <int NS>
-__global__ __launch_bounds__(256) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
+__global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
                                                WorkArgs ws, OutArgs out, int bin, int single) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);

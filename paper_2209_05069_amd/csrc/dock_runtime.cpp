@@ -66,7 +66,8 @@ struct Ticket {
     dock_results user{};
     int L = 0, K = 0, R = 0;
     long long A = 0, trace_len = 0;
-    void *host_stage = nullptr;      // pinned copy of the results
+    void *pinned = nullptr;          // pinned inputs followed by the results
+    void *host_stage = nullptr;      // results part of `pinned`
     size_t stage_bytes = 0;
     // offsets of the result arrays inside host_stage
     size_t o_best, o_np, o_st, o_ps, o_pr, o_xyz, o_rs, o_tr, o_ft;
@@ -136,7 +137,9 @@ int check_library_shape(const dock_library *lib) {
     if (lib->mask_words < 1 || lib->mask_words > 4) return fail(DOCK_EINVAL, "mask_words must be in [1,4]");
     if (lib->n_atoms_total < 0 || lib->n_bonds_total < 0 || lib->n_rot_total < 0)
         return fail(DOCK_EINVAL, "negative totals");
-    if (lib->n_atoms_total > ((long long)1 << 31) / 64) return fail(DOCK_EINVAL, "n_atoms_total too large");
+    if (lib->n_atoms_total >= ((long long)1 << 31) || lib->n_bonds_total >= ((long long)1 << 31) ||
+        lib->n_rot_total >= ((long long)1 << 31))
+        return fail(DOCK_EINVAL, "totals must be below 2^31 (int32 offsets)");
     if (lib->n_ligands > 0) {
         if (!lib->atom_off || !lib->bond_off || !lib->rot_off)
             return fail(DOCK_EINVAL, "offset array is NULL");
@@ -268,6 +271,7 @@ constexpr int kDockWaves = 4;
 constexpr int kFinalWaves = 4;
 
 constexpr int kPlainWaves = 4;
+constexpr int kPlainFinalWaves = 16;  // plain form: kept poses of one ligand spread over 16 waves
 constexpr int kSubmitStreams = 4;
 constexpr int kPlainStreams = 4;
 
@@ -305,7 +309,7 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
         if (n < 1 || n > kMaxAtoms) continue;  // flagged by the checks
         const int bin = (n - 1) >> 5;
         HIP_TRY(launch_plain(l, bin, kPlainWaves, g, sa, la, wa, oa, t));
-        HIP_TRY(launch_final(bin, 1, kFinalWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_final(bin, 1, kPlainFinalWaves, g, sa, la, wa, oa, l, t));
     }
     for (size_t i = 0; i < c->plain_streams.size(); ++i) {
         HIP_TRY(hipEventRecord(c->plain_events[i], c->plain_streams[i]));
@@ -490,7 +494,7 @@ int dock_destroy(dock_ctx *c) {
     hipDeviceSynchronize();
     for (auto &kv : c->tickets) {
         if (kv.second.done) hipEventDestroy(kv.second.done);
-        if (kv.second.host_stage) hipHostFree(kv.second.host_stage);
+        if (kv.second.pinned) hipHostFree(kv.second.pinned);
     }
     for (auto &kv : c->pockets) hipFree(kv.second.d_cubes);
     for (auto &kv : c->ws) hipFree(kv.second.base);
@@ -656,30 +660,35 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
         (void)hipGetLastError();
         return fail(DOCK_EAGAIN, "device allocation failed");
     }
-    if (hipHostMalloc(&t.host_stage, so > 0 ? so : 256, hipHostMallocDefault) != hipSuccess) {
+    // one pinned buffer per ticket: the inputs (same layout as on the device, so
+    // one copy moves them all) followed by the results
+    void *pinned = nullptr;
+    if (hipHostMalloc(&pinned, off + (so > 0 ? so : 256), hipHostMallocDefault) != hipSuccess) {
         hipFreeAsync(d, s);
         return fail(DOCK_ENOMEM, "pinned staging allocation failed");
     }
-    // inputs: copied before return (pageable source -> the copy completes before the call returns)
-    auto up = [&](size_t at, const void *src, size_t b) -> hipError_t {
-        if (b == 0) return hipSuccess;
-        return hipMemcpyAsync(d + at, src, b, hipMemcpyHostToDevice, s);
+    t.host_stage = (char *)pinned + off;
+    t.pinned = pinned;
+    // inputs are copied into pinned memory before return: the caller may free its own
+    char *h = (char *)pinned;
+    auto put = [&](size_t at, const void *src, size_t b) {
+        if (b) std::memcpy(h + at, src, b);
     };
-    hipError_t e = hipSuccess;
     if (L > 0) {
-        e = up(i_ao, lib->atom_off, (size_t)(L + 1) * 4);
-        if (!e) e = up(i_xyz, lib->xyz, (size_t)A * 12);
-        if (!e) e = up(i_ty, lib->type, (size_t)A);
-        if (!e) e = up(i_bo, lib->bond_off, (size_t)(L + 1) * 4);
-        if (!e) e = up(i_b, lib->bond, (size_t)Nb * 8);
-        if (!e) e = up(i_ro, lib->rot_off, (size_t)(L + 1) * 4);
-        if (!e) e = up(i_rb, lib->rot_bond, (size_t)Nr * 8);
-        if (!e) e = up(i_rm, lib->rot_mask, (size_t)Nr * lib->mask_words * 8);
+        put(i_ao, lib->atom_off, (size_t)(L + 1) * 4);
+        put(i_xyz, lib->xyz, (size_t)A * 12);
+        put(i_ty, lib->type, (size_t)A);
+        put(i_bo, lib->bond_off, (size_t)(L + 1) * 4);
+        put(i_b, lib->bond, (size_t)Nb * 8);
+        put(i_ro, lib->rot_off, (size_t)(L + 1) * 4);
+        put(i_rb, lib->rot_bond, (size_t)Nr * 8);
+        put(i_rm, lib->rot_mask, (size_t)Nr * lib->mask_words * 8);
     }
-    if (!e) e = hipStreamSynchronize(s);  // caller may free its inputs after return
+    hipError_t e = off ? hipMemcpyAsync(d, h, off, hipMemcpyHostToDevice, s) : hipSuccess;
     if (e) {
+        hipStreamSynchronize(s);
         hipFreeAsync(d, s);
-        hipHostFree(t.host_stage);
+        hipHostFree(pinned);
         return fail(DOCK_EDEVICE, std::string("input copy failed: ") + hipGetErrorString(e));
     }
     dock_library dl = *lib;
@@ -706,7 +715,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (rc2) {
         hipStreamSynchronize(s);
         hipFreeAsync(d, s);
-        hipHostFree(t.host_stage);
+        hipHostFree(pinned);
         return rc2;
     }
     e = hipMemcpyAsync(t.host_stage, dr, so, hipMemcpyDeviceToHost, s);
@@ -715,7 +724,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (!e) e = hipEventRecord(t.done, s);
     if (e) {
         hipStreamSynchronize(s);
-        hipHostFree(t.host_stage);
+        hipHostFree(pinned);
         return fail(DOCK_EDEVICE, std::string("enqueue failed: ") + hipGetErrorString(e));
     }
     t.pocket = pocket;
@@ -744,7 +753,7 @@ static int finish_ticket(dock_ctx *c, std::map<uint64_t, Ticket>::iterator it) {
         if (u.final_trace) std::memcpy(u.final_trace, h + t.o_ft, L * K * 2);
     }
     hipEventDestroy(t.done);
-    hipHostFree(t.host_stage);
+    hipHostFree(t.pinned);
     auto pk = c->pockets.find(t.pocket);
     if (pk != c->pockets.end() && pk->second.busy > 0) pk->second.busy -= 1;
     c->tickets.erase(it);

@@ -14,4 +14,5 @@ from .synth import (  # noqa: F401
     start_quats,
     config,
     CONFIGS,
+    MASTER_SEED,
 )
