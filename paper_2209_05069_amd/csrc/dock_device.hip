@@ -606,7 +606,7 @@ static __device__ __forceinline__ size_t trace_base(const LibArgs &lib, const Se
 
 // ---------------------------------------------------------------------------
 // Docking kernel: persistent workgroups pop (ligand, restart-group) items of one
-// size bin; each wave docks one restart.
+// size bin; each wave docks one restart from the orientation k_align chose.
 template <int NS, int C>
 __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
                                               int bin) {
@@ -650,8 +650,9 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
             Pose<NS> Y;
             start_pose(Y, xyzt, n, r, g, sa);
             uint16_t *tr_out = ws.rtrace + trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B);
-            const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, WaveSplit());
-            if (lane == 0) tr_out[0] = (uint16_t)o;
+            // the alignment step was taken by k_align (first trace entry)
+            const int o = uniform_int((int)tr_out[0]);
+            apply_align(Y, n, o < sa.A * sa.A ? o : 0, sa);
             int d = 1;
             for (int p = 0; p < sa.P; ++p) {
                 for (int b = 0; b < B; ++b, ++d) {
@@ -664,6 +665,473 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
             }
             const float sc = pose_score(Y, n, toff, tr, g);
             if (lane == 0) ws.rscore[(size_t)l * sa.R + r] = sc;
+        }
+        __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Batched rigid alignment (Rigid Rotation of Alg. 1) from sphere shells in LDS.
+//
+// Every alignment sample of atom a lies on the sphere of radius |Y_a - c| about
+// the pose centroid c, and Generate_Starting_Pose puts c at the grid centre for
+// every restart and every ligand.  So the grid cells a sample can fall in
+// depend only on the atom type and that radius.  At pocket load the shell
+// atlas stores, per type and per radius band of kBandWidth cells (thickened by
+// kShellPad on both sides), the cells the band crosses as "corner columns":
+// for vertex x-position i of cell row (j,k) the float4 (v(i,j,k), v(i,j+1,k),
+// v(i,j,k+1), v(i,j+1,k+1)); cell (i,j,k) is the two consecutive columns i and
+// i+1.  A row table indexed by (j,k) gives each row's cell range on the low-x
+// and the high-x side of the centre.  A workgroup of k_align aligns G restarts
+// of one ligand: per atom it copies that atom's band into LDS (prefetched into
+// registers while the previous atom is sampled), and all G * A * A samples of
+// the atom read LDS.  A sample whose cell is not in the band reads its cube from
+// global memory; both give the same eight values, and the transform, blend and
+// atom-order sum are those of align_pose, so the scores are bit-identical.
+constexpr float kShellPad = 0.0625f;
+constexpr float kBandWidth = 0.125f;
+constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
+constexpr int kShellPrefetch = 4;       // float4 per thread prefetched for the next atom
+constexpr int kShellBatch = 4;          // samples scheduled together
+
+// Side entry of a row: bits 0-13 first column (relative to the band's columns),
+// 14-21 first cell x, 22-29 number of cells (0: empty side).
+__device__ __forceinline__ int seg_entry(int base, int lo, int len) {
+    return len > 0 ? (base | (lo << 14) | (len << 22)) : 0;
+}
+
+struct RowShell {
+    int nlo, nhi, plo, phi;  // cell x ranges, low and high side; empty: lo > hi
+    bool merged;             // one segment serves both sides
+    __device__ int cols_n() const { return nhi >= nlo ? nhi - nlo + 2 : 0; }
+    __device__ int cols_p() const { return (!merged && phi >= plo) ? phi - plo + 2 : 0; }
+};
+
+// Cells of row (iy, iz) crossed by the shell rlo <= |p - ec| <= rhi (grid units).
+__device__ RowShell shell_row(int iy, int iz, float ecx, float ecy, float ecz, float rlo2,
+                              float rhi2, const GridArgs &g) {
+    RowShell r{1, 0, 1, 0, false};
+    if (iy < 0 || iy > g.ny - 2 || iz < 0 || iz > g.nz - 2) return r;
+    const float ya = (float)iy - ecy, yb = ya + 1.0f;
+    const float za = (float)iz - ecz, zb = za + 1.0f;
+    const float dy0 = ya > 0.0f ? ya : (yb < 0.0f ? -yb : 0.0f);
+    const float dz0 = za > 0.0f ? za : (zb < 0.0f ? -zb : 0.0f);
+    const float dy1 = fmaxf(fabsf(ya), fabsf(yb)), dz1 = fmaxf(fabsf(za), fabsf(zb));
+    const float dmin2 = dy0 * dy0 + dz0 * dz0, dmax2 = dy1 * dy1 + dz1 * dz1;
+    if (dmin2 > rhi2) return r;
+    const float xa = sqrtf(fmaxf(rlo2 - dmax2, 0.0f)), xb = sqrtf(rhi2 - dmin2);
+    r.nlo = max((int)floorf(ecx - xb), 0);
+    r.nhi = min((int)floorf(ecx - xa), g.nx - 2);
+    r.plo = max((int)floorf(ecx + xa), 0);
+    r.phi = min((int)floorf(ecx + xb), g.nx - 2);
+    if (r.nlo > r.nhi) {  // only the high side: keep it as the segment of both sides
+        r.nlo = r.plo;
+        r.nhi = r.phi;
+        r.merged = true;
+    } else if (r.plo > r.phi) {
+        r.merged = true;
+    } else if (r.nhi + 1 >= r.plo) {
+        r.nhi = max(r.nhi, r.phi);
+        r.merged = true;
+    }
+    return r;
+}
+
+struct BandGeom {
+    int y0, z0, thy, thz;
+    float rlo2, rhi2;
+};
+
+__device__ __forceinline__ BandGeom band_geom(int b, float ecy, float ecz) {
+    BandGeom q;
+    const float rlo = fmaxf((float)b * kBandWidth - kShellPad, 0.0f);
+    const float rhi = (float)(b + 1) * kBandWidth + kShellPad;
+    q.rlo2 = rlo * rlo;
+    q.rhi2 = rhi * rhi;
+    q.y0 = (int)floorf(ecy - rhi) - 1;
+    q.z0 = (int)floorf(ecz - rhi) - 1;
+    q.thy = (int)floorf(ecy + rhi) + 1 - q.y0 + 1;
+    q.thz = (int)floorf(ecz + rhi) + 1 - q.z0 + 1;
+    return q;
+}
+
+// Atlas pass 1 (one workgroup of 1024 per band): band geometry and column count.
+// info[2b] = (y0, z0, thy, thz), info[2b+1] = (rows, ncols or -1, table bytes, 0).
+__global__ __launch_bounds__(1024) void k_atlas_count(GridArgs g, int4 *info) {
+    __shared__ int wsum[16];
+    const int b = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
+    const BandGeom q = band_geom(b, g.acy, g.acz);
+    const int rows = q.thy * q.thz;
+    const int per = (rows + (int)blockDim.x - 1) / (int)blockDim.x;
+    int local = 0;
+    if (per <= kShellRowsPerThread) {
+        for (int k = 0; k < per; ++k) {
+            const int t = tid * per + k;
+            if (t < rows) {
+                const RowShell r = shell_row(q.y0 + t / q.thz, q.z0 + t % q.thz, g.acx, g.acy,
+                                             g.acz, q.rlo2, q.rhi2, g);
+                local += r.cols_n() + r.cols_p();
+            }
+        }
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) local += __shfl_xor(local, o, 64);
+    if (lane == 0) wsum[wave] = local;
+    __syncthreads();
+    if (tid == 0) {
+        int total = 0;
+        for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wsum[w];
+        const bool ok = per <= kShellRowsPerThread && total < (1 << 14);
+        info[2 * b] = make_int4(q.y0, q.z0, q.thy, q.thz);
+        info[2 * b + 1] = make_int4(rows, ok ? total : -1, (rows * 8 + 15) & ~15, 0);
+    }
+}
+
+// Atlas pass 2 (one workgroup of 1024 per (type, band)): the row table and the
+// corner columns of the band, from the corner cubes.  blob16[t*nb + b] is the
+// band's offset in float4 units.
+__global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *info,
+                                                     const int *blob16, float4 *atlas, int nb) {
+    __shared__ int pre[kShellRowsPerThread * 1024 + 1];
+    __shared__ int wsum[16];
+    const int t = blockIdx.x / nb, b = blockIdx.x - t * nb;
+    const int tid = threadIdx.x, lane = lane_id(), wave = tid >> 6, BD = blockDim.x;
+    const int4 i1 = info[2 * b + 1];
+    if (i1.y < 0) return;
+    const BandGeom q = band_geom(b, g.acy, g.acz);
+    const int rows = i1.x, per = (rows + BD - 1) / BD;
+    int2 *table = (int2 *)(atlas + blob16[blockIdx.x]);
+    float4 *col = atlas + blob16[blockIdx.x] + i1.z / 16;
+    int cnt[kShellRowsPerThread];
+    int local = 0;
+#pragma unroll
+    for (int k = 0; k < kShellRowsPerThread; ++k) {
+        cnt[k] = 0;
+        const int r = tid * per + k;
+        if (k < per && r < rows) {
+            const RowShell s = shell_row(q.y0 + r / q.thz, q.z0 + r % q.thz, g.acx, g.acy, g.acz,
+                                         q.rlo2, q.rhi2, g);
+            cnt[k] = s.cols_n() + s.cols_p();
+        }
+        local += cnt[k];
+    }
+    int incl = local;
+#pragma unroll
+    for (int o = 1; o < 64; o <<= 1) {
+        const int v = __shfl_up(incl, o, 64);
+        if (lane >= o) incl += v;
+    }
+    if (lane == 63) wsum[wave] = incl;
+    __syncthreads();
+    int run = incl - local;
+    for (int w = 0; w < wave; ++w) run += wsum[w];
+#pragma unroll
+    for (int k = 0; k < kShellRowsPerThread; ++k) {
+        const int r = tid * per + k;
+        if (k < per && r < rows) {
+            pre[r] = run;
+            const RowShell s = shell_row(q.y0 + r / q.thz, q.z0 + r % q.thz, g.acx, g.acy, g.acz,
+                                         q.rlo2, q.rhi2, g);
+            const int cn = s.cols_n();
+            const int en = seg_entry(run, s.nlo, cn > 0 ? s.nhi - s.nlo + 1 : 0);
+            const int ep = s.merged ? en
+                                    : seg_entry(run + cn, s.plo, s.phi >= s.plo ? s.phi - s.plo + 1 : 0);
+            table[r] = make_int2(en, ep);
+            run += cnt[k];
+        }
+    }
+    __syncthreads();
+    for (int v = tid; v < i1.y; v += BD) {
+        int lo = 0, hi = rows - 1;  // last row whose first column is <= v
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (pre[mid] <= v) lo = mid;
+            else hi = mid - 1;
+        }
+        const int iy = q.y0 + lo / q.thz, iz = q.z0 + lo % q.thz;
+        const RowShell s = shell_row(iy, iz, g.acx, g.acy, g.acz, q.rlo2, q.rhi2, g);
+        const int u = v - pre[lo], cn = s.cols_n();
+        const int i = u < cn ? s.nlo + u : s.plo + (u - cn);
+        const size_t e = ((size_t)t * g.nz * g.ny + (size_t)iz * g.ny + iy) * g.nx + i;
+        const float4 q0 = g.cubes[2 * e], q1 = g.cubes[2 * e + 1];
+        col[v] = make_float4(q0.x, q0.z, q1.x, q1.z);
+    }
+}
+
+// Shared-memory layout of k_align (bytes).
+struct AlignLds {
+    static __host__ __device__ size_t xyzt() { return 0; }
+    static __host__ __device__ size_t recs(int nmax) { return (size_t)nmax * 16; }
+    static __host__ __device__ size_t ectr(int nmax, int G) {
+        return recs(nmax) + (size_t)nmax * G * 16;
+    }
+    static __host__ __device__ size_t ainf(int nmax, int G) { return ectr(nmax, G) + (size_t)G * 16; }
+    static __host__ __device__ size_t misc(int nmax, int G) { return ainf(nmax, G) + (size_t)nmax * 32; }
+    static __host__ __device__ size_t best(int nmax, int G) { return misc(nmax, G) + 128; }
+    static __host__ __device__ size_t region(int nmax, int G) {
+        return (best(nmax, G) + (size_t)G * 8 + 15) & ~(size_t)15;
+    }
+};
+
+struct Shell {
+    int y0, z0, thy, thz, rows;
+    float cx;             // centre x (grid units): side of a sample
+    const int2 *table;    // [thy*thz] (low-side entry, high-side entry)
+    const float4 *col;    // corner columns
+};
+
+// Trilinear sample of grid coordinates (gx,gy,gz) from the shell.  Returns false
+// (and leaves v undefined) when the cell is not in the shell.  Clamp = false
+// when every sample of the shell is inside [0, n-2] on each axis, where the
+// clamps of tri_u are the identity.  Same arithmetic as tri_u otherwise.
+template <bool Clamp>
+__device__ __forceinline__ bool shell_sample(const Shell &s, const Tri &t, float gx, float gy,
+                                             float gz, float &v) {
+    float cx = gx, cy = gy, cz = gz, ix, iy, iz;
+    if (Clamp) {
+        cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
+        cy = __builtin_amdgcn_fmed3f(gy, 0.0f, t.my);
+        cz = __builtin_amdgcn_fmed3f(gz, 0.0f, t.mz);
+        ix = floorf(__builtin_amdgcn_fmed3f(gx, 0.0f, t.m2x));
+        iy = floorf(__builtin_amdgcn_fmed3f(gy, 0.0f, t.m2y));
+        iz = floorf(__builtin_amdgcn_fmed3f(gz, 0.0f, t.m2z));
+    } else {
+        ix = floorf(gx);
+        iy = floorf(gy);
+        iz = floorf(gz);
+    }
+    const float fx = cx - ix, fy = cy - iy, fz = cz - iz;
+    const int jy = (int)iy - s.y0, kz = (int)iz - s.z0;
+    const bool rin = (unsigned)jy < (unsigned)s.thy && (unsigned)kz < (unsigned)s.thz;
+    // row index clamped into the table; a row outside it counts as empty
+    const unsigned ri = min((unsigned)(__mul24(jy, s.thz) + kz), (unsigned)s.rows - 1u);
+    const int2 e2 = s.table[ri];
+    const unsigned e = (unsigned)(gx < s.cx ? e2.x : e2.y) & (0u - (unsigned)rin);
+    const int d = (int)ix - (int)((e >> 14) & 255u);
+    const bool hit = (unsigned)d < (e >> 22);
+    const int addr = hit ? (int)(e & 0x3FFFu) + d : 0;
+    const float4 A = s.col[addr], B = s.col[addr + 1];
+    const float c00 = fmaf(fx, B.x - A.x, A.x);
+    const float c10 = fmaf(fx, B.y - A.y, A.y);
+    const float c01 = fmaf(fx, B.z - A.z, A.z);
+    const float c11 = fmaf(fx, B.w - A.w, A.w);
+    const float c0 = fmaf(fy, c10 - c00, c00);
+    const float c1 = fmaf(fy, c11 - c01, c01);
+    v = fmaf(fz, c1 - c0, c0);
+    return hit;
+}
+
+// The G samples of one atom (record row ra, centres ectr) for the orientation
+// rows m0..m2, added to acc in restart order.  A sample whose cell is not in the
+// shell adds -0 (the exact identity) and is redone from global memory before
+// any later addition to its accumulator, so every sum keeps atom order.
+template <int G, bool Clamp>
+__device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, const Tri &tr,
+                                           const float4 *ra, const float4 *ectr, float4 m0,
+                                           float4 m1, float4 m2, int to) {
+    unsigned miss = 0u;
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) {
+        const float4 r = ra[gg], e = ectr[gg];
+        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+        float v;
+        const bool hit = shell_sample<Clamp>(sh, tr, gx, gy, gz, v);
+        acc[gg] += hit ? v : -0.0f;
+        miss |= hit ? 0u : (1u << gg);
+        // keep the scheduler from hoisting every sample's loads (register spills)
+        if ((gg & (kShellBatch - 1)) == kShellBatch - 1) __builtin_amdgcn_sched_barrier(0);
+    }
+    // materialise the sums here (else the compiler defers them past the branch
+    // below and keeps every sample's inputs live)
+#pragma unroll
+    for (int gg = 0; gg < G; ++gg) asm volatile("" : "+v"(acc[gg]));
+    if (__ballot(miss != 0u) != 0ull) {
+        // recompute the coordinates rather than keep the first pass's G sets
+        // live across it (an opaque zero offset stops the compiler merging them)
+        int z = 0;
+        asm volatile("" : "+v"(z));
+#pragma unroll
+        for (int gg = 0; gg < G; ++gg) {
+            if ((miss >> gg) & 1u) {
+                const float4 r = ra[gg + z], e = ectr[gg + z];
+                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+                acc[gg] += tri_u(tr, gx, gy, gz, to);
+            }
+        }
+    }
+}
+
+// Persistent workgroups pop (ligand, group of G restarts) items of one size bin
+// and write each restart's best orientation as the first entry of its decision
+// trace; k_dock then starts from it.  Lanes hold orientations (blockDim.x per
+// chunk), each with G score accumulators.
+template <int NS, int G>
+__global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
+                                                int bin, int arena) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nmax = bin_nmax(bin);
+    const int BD = blockDim.x, W = BD >> 6, tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    float4 *xyzt = (float4 *)(smem + AlignLds::xyzt());
+    float4 *recs = (float4 *)(smem + AlignLds::recs(nmax));
+    float4 *ectr = (float4 *)(smem + AlignLds::ectr(nmax, G));
+    int4 *ainf = (int4 *)(smem + AlignLds::ainf(nmax, G));  // per atom: band copy, band rows
+    int *misc = (int *)(smem + AlignLds::misc(nmax, G));
+    u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, G));
+    float4 *region = (float4 *)(smem + AlignLds::region(nmax, G));
+    const int region16 = (arena - (int)AlignLds::region(nmax, G)) / 16;
+    const Tri tr = make_tri(g);
+    const int groups = (sa.R + G - 1) / G;
+    const long long total = (long long)ws.counters[bin] * groups;
+    const int NO = sa.A * sa.A;
+    for (;;) {
+        if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
+        __syncthreads();
+        const int item = misc[0];
+        if ((long long)item >= total) break;
+        const int li = item / groups, grp = item - li * groups;
+        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+        const int B = lib.rot_off[l + 1] - lib.rot_off[l];
+        const int rbase = grp * G;
+        for (int i = tid; i < n; i += BD) {
+            const float *p = lib.xyz + 3 * (size_t)(a0 + i);
+            const uint32_t toff = (uint32_t)lib.type[a0 + i] * g.type_bytes;
+            xyzt[i] = make_float4(p[0], p[1], p[2], __uint_as_float(toff));
+        }
+        if (tid < G) bestk[tid] = 0ull;
+        __syncthreads();
+        for (int gg = wave; gg < G; gg += W) {
+            // restarts past R (last group) repeat the group's first restart
+            const int r = rbase + gg < sa.R ? rbase + gg : rbase;
+            {
+                Pose<NS> Y;
+                start_pose(Y, xyzt, n, r, g, sa);
+                float cx, cy, cz;
+                centroid(Y, n, cx, cy, cz);
+#pragma unroll
+                for (int q = 0; q < NS; ++q) {
+                    const int i = lane + 64 * q;
+                    if (i < n)
+                        recs[i * G + gg] = make_float4((Y.x[q] - cx) * g.inv_h,
+                                                       (Y.y[q] - cy) * g.inv_h,
+                                                       (Y.z[q] - cz) * g.inv_h, 0.0f);
+                }
+                if (lane == 0)
+                    ectr[gg] = make_float4((cx - g.ox) * g.inv_h, (cy - g.oy) * g.inv_h,
+                                           (cz - g.oz) * g.inv_h, 0.0f);
+            }
+        }
+        __syncthreads();
+        // each atom's band in the atlas (radius from the group's first restart)
+        for (int a = tid; a < n; a += BD) {
+            const float4 rc = recs[a * G];
+            const float rg = sqrtf(fmaf(rc.x, rc.x, fmaf(rc.y, rc.y, rc.z * rc.z)));
+            const int b = (int)(rg * (1.0f / kBandWidth));
+            int4 c0 = make_int4(-1, 0, 0, 0), c1 = make_int4(0, 0, 0, 0);
+            if (b < g.nbands) {
+                const int4 gi = g.bands[2 * b], gj = g.bands[2 * b + 1];
+                const int size16 = gj.z / 16 + gj.y;
+                const int t = (int)(lib.type[a0 + a]);
+                if (gj.y >= 0 && size16 <= region16) {
+                    // clamps are the identity when the sphere (half a cell of
+                    // margin) stays inside [0, n-2] on every axis
+                    const float4 e = ectr[0];
+                    const float m = rg + 0.5f;
+                    const bool inside = e.x - m >= 0.0f && e.y - m >= 0.0f && e.z - m >= 0.0f &&
+                                        e.x + m <= g.m2x && e.y + m <= g.m2y && e.z + m <= g.m2z;
+                    c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
+                    c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
+                }
+            }
+            ainf[2 * a] = c0;
+            ainf[2 * a + 1] = c1;
+        }
+        __syncthreads();
+        for (int obase = 0; obase < NO; obase += BD) {
+            const int o = obase + tid;
+            const bool ov = o < NO;
+            const int oo = ov ? o : 0;
+            const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1],
+                         m2 = sa.amat[3 * oo + 2];
+            float acc[G];
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) acc[gg] = 0.0f;
+            float4 pf[kShellPrefetch];
+            // copy the first atom's band
+            {
+                const int4 c0 = ainf[0];
+                if (c0.x >= 0)
+                    for (int k = tid; k < c0.y; k += BD) region[k] = g.atlas[c0.x + k];
+            }
+            __syncthreads();
+            for (int a = 0; a < n; ++a) {
+                const int4 cn = a + 1 < n ? ainf[2 * (a + 1)] : make_int4(-1, 0, 0, 0);
+#pragma unroll
+                for (int k = 0; k < kShellPrefetch; ++k) {
+                    const int idx = tid + k * BD;
+                    if (cn.x >= 0 && idx < cn.y) pf[k] = g.atlas[cn.x + idx];
+                }
+                const int to = uniform_int(__float_as_int(xyzt[a].w));
+                const int4 c0 = ainf[2 * a], c1 = ainf[2 * a + 1];
+                const float4 *ra = recs + a * G;
+                const float4 *ec = ectr;
+                if (c0.x >= 0) {
+                    Shell sh;
+                    sh.y0 = c0.z;
+                    sh.z0 = c0.w;
+                    sh.thy = c1.x;
+                    sh.thz = c1.y;
+                    sh.rows = c1.x * c1.y;
+                    sh.cx = g.acx;
+                    sh.table = (const int2 *)region;
+                    sh.col = region + c1.z;
+                    if (c1.w) shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                    else shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                } else {
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        const float4 r = ra[gg], e = ec[gg];
+                        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+                        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+                        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+                        acc[gg] += tri_u(tr, gx, gy, gz, to);
+                    }
+                }
+                __syncthreads();  // every sample of atom a has read the region
+                if (cn.x >= 0) {
+#pragma unroll
+                    for (int k = 0; k < kShellPrefetch; ++k) {
+                        const int idx = tid + k * BD;
+                        if (idx < cn.y) region[idx] = pf[k];
+                    }
+                    for (int k = tid + kShellPrefetch * BD; k < cn.y; k += BD)
+                        region[k] = g.atlas[cn.x + k];
+                }
+                __syncthreads();
+            }
+            u64 *slots = (u64 *)region;
+#pragma unroll
+            for (int gg = 0; gg < G; ++gg) {
+                u64 key = ov ? make_key(acc[gg], (uint32_t)o) : 0ull;
+                key = wave_max_u64(key);
+                if (lane == 0) slots[wave * G + gg] = key;
+            }
+            __syncthreads();
+            if (tid < G) {
+                u64 b = bestk[tid];
+                for (int w = 0; w < W; ++w) b = slots[w * G + tid] > b ? slots[w * G + tid] : b;
+                bestk[tid] = b;
+            }
+            __syncthreads();
+        }
+        if (tid < G && rbase + tid < sa.R) {
+            const int r = rbase + tid;
+            ws.rtrace[trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B)] =
+                (uint16_t)key_index(bestk[tid]);
         }
         __syncthreads();
     }
@@ -1067,7 +1535,7 @@ __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs 
 }
 
 __global__ void k_reset(int *counters) {
-    if (threadIdx.x < 3 * kNumBins) counters[threadIdx.x] = 0;
+    if (threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -1079,6 +1547,19 @@ hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, in
     const long long blocks = (n + threads - 1) / threads;
     hipLaunchKernelGGL(k_build_cubes, dim3((unsigned)blocks), dim3(threads), 0, s, values, cubes,
                        ntypes, nx, ny, nz);
+    return hipGetLastError();
+}
+
+hipError_t launch_atlas_count(const GridArgs &g, int4 *info, hipStream_t s) {
+    hipLaunchKernelGGL(k_atlas_count, dim3(kMaxBands), dim3(1024), 0, s, g, info);
+    return hipGetLastError();
+}
+
+hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blob16, float4 *atlas,
+                             int nb, hipStream_t s) {
+    if (nb <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_atlas_fill, dim3(nb * g.ntypes), dim3(1024), 0, s, g, info, blob16, atlas,
+                       nb);
     return hipGetLastError();
 }
 
@@ -1188,6 +1669,82 @@ hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const
         case 2: return launch_final_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
         case 3: return launch_final_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
         default: return launch_final_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+    }
+}
+
+template <int NS, int G>
+static hipError_t launch_align_t(int bin, int blocks, int waves, int arena,
+                                 const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                                 const WorkArgs &ws, hipStream_t s) {
+    hipFuncSetAttribute((const void *)k_align<NS, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        arena);
+    hipLaunchKernelGGL((k_align<NS, G>), dim3(blocks), dim3(64 * waves), (size_t)arena, s, g, sa,
+                       lib, ws, bin, arena);
+    return hipGetLastError();
+}
+
+template <int NS>
+static hipError_t launch_align_g(int bin, int G, int blocks, int waves, int arena,
+                                 const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                                 const WorkArgs &ws, hipStream_t s) {
+    if (G <= 8) return launch_align_t<NS, 8>(bin, blocks, waves, arena, g, sa, lib, ws, s);
+    if (G <= 16) return launch_align_t<NS, 16>(bin, blocks, waves, arena, g, sa, lib, ws, s);
+    return launch_align_t<NS, 32>(bin, blocks, waves, arena, g, sa, lib, ws, s);
+}
+
+int align_group(int bin, int R) {
+    const int nmax = bin_nmax(bin);
+    int G = nmax <= 64 ? 32 : (nmax <= 128 ? 16 : 8);
+    while (G > 8 && G / 2 >= R) G /= 2;
+    return G;
+}
+
+int align_waves(int A) {
+    const int w = (A * A + 63) / 64;
+    return w < 4 ? 4 : (w > 16 ? 16 : w);
+}
+
+size_t align_lds_min(int bin, int R) {
+    return AlignLds::region(bin_nmax(bin), align_group(bin, R)) + 1024;
+}
+
+hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
+                        const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                        hipStream_t s) {
+    const int G = align_group(bin, sa.R), waves = align_waves(sa.A);
+    switch (bin_slots(bin)) {
+        case 1: return launch_align_g<1>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
+        case 2: return launch_align_g<2>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
+        case 3: return launch_align_g<3>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
+        default: return launch_align_g<4>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
+    }
+}
+
+template <int NS, int G>
+static int align_occ_t(int waves, int arena) {
+    int nb = 0;
+    hipFuncSetAttribute((const void *)k_align<NS, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        arena);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align<NS, G>, 64 * waves,
+                                                     (size_t)arena) != hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+template <int NS>
+static int align_occ_g(int G, int waves, int arena) {
+    if (G <= 8) return align_occ_t<NS, 8>(waves, arena);
+    if (G <= 16) return align_occ_t<NS, 16>(waves, arena);
+    return align_occ_t<NS, 32>(waves, arena);
+}
+
+int align_blocks_per_cu(int bin, int R, int A, int arena) {
+    const int G = align_group(bin, R), waves = align_waves(A);
+    switch (bin_slots(bin)) {
+        case 1: return align_occ_g<1>(G, waves, arena);
+        case 2: return align_occ_g<2>(G, waves, arena);
+        case 3: return align_occ_g<3>(G, waves, arena);
+        default: return align_occ_g<4>(G, waves, arena);
     }
 }
 

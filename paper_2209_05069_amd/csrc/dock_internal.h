@@ -11,6 +11,7 @@ constexpr int kMaxRot = 64;
 constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+1)
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
+constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, final_next, align_next
 
 // The pocket is kept as corner cubes: cube (t,k,j,i) = the grid values of type
 // t at (i,j,k), (i+1,j,k), (i,j+1,k), (i+1,j+1,k), then the same four of slab
@@ -26,6 +27,14 @@ struct GridArgs {
     float mx, my, mz;      // n-1 per axis
     float m2x, m2y, m2z;   // n-2 per axis
     float fnx, fslab;      // nx and nx*ny as floats
+    // Shell atlas (see k_align): per radius band b < nbands, bands[2b] = (y0, z0,
+    // rows in y, rows in z), bands[2b+1] = (rows, columns or -1, table bytes, 0);
+    // blob16[t*nbands + b] = float4 offset of type t's band in `atlas`.
+    const float4 *atlas;
+    const int4 *bands;
+    const int *blob16;
+    int nbands;
+    float acx, acy, acz;   // grid centre in grid units
 };
 
 struct SearchArgs {
@@ -52,7 +61,7 @@ struct LibArgs {
 
 struct WorkArgs {
     unsigned long long *far;  // [A_total][kFarWords]
-    int *counters;            // [3*kNumBins]: bin_count, dock_next, final_next
+    int *counters;            // [kNumCounters]: bin_count, dock_next, final_next, align_next
     int *bin_list;            // [kNumBins][L]
     float *rscore;            // [L][R]
     uint16_t *rtrace;         // [R*(L + P*Nr_total)]
@@ -83,6 +92,20 @@ hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &l
                        const WorkArgs &ws, const OutArgs &out, hipStream_t s);
 hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                        const LibArgs &lib, const WorkArgs &ws, hipStream_t s);
+// Shell atlas of a pocket: pass 1 writes the geometry of kMaxBands bands into
+// info[2*kMaxBands]; pass 2 fills nb bands of every type.
+constexpr int kMaxBands = 240;
+hipError_t launch_atlas_count(const GridArgs &g, int4 *info, hipStream_t s);
+hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blob16, float4 *atlas,
+                             int nb, hipStream_t s);
+// Batched alignment of a bin's ligands (k_align), `arena` bytes of LDS per
+// workgroup.
+hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
+                        const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                        hipStream_t s);
+// Smallest arena k_align accepts for the bin (fixed part plus a minimal region).
+size_t align_lds_min(int bin, int R);
+int align_blocks_per_cu(int bin, int R, int A, int arena);
 // single >= 0: only that ligand (plain form), else the bin's queue.
 hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,

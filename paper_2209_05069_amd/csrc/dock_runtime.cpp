@@ -44,8 +44,20 @@ int fail(int code, const std::string &msg) {
 
 struct Pocket {
     float4 *d_cubes = nullptr;
+    float4 *d_atlas = nullptr;
+    int4 *d_bands = nullptr;
+    int *d_blob16 = nullptr;
     GridArgs g{};
     int busy = 0;
+    void release() {
+        hipFree(d_cubes);
+        hipFree(d_atlas);
+        hipFree(d_bands);
+        hipFree(d_blob16);
+        d_cubes = d_atlas = nullptr;
+        d_bands = nullptr;
+        d_blob16 = nullptr;
+    }
 };
 
 struct Workspace {
@@ -78,6 +90,7 @@ struct Ticket {
 struct dock_ctx {
     int device = 0;
     int num_cu = 0;
+    int lds_arena = 0;  // LDS bytes per workgroup of the alignment kernel
     std::mutex mu;
     std::map<int32_t, Pocket> pockets;
     int32_t next_pocket = 1;
@@ -224,7 +237,7 @@ WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trac
     size_t o = 0;
     const size_t L = (size_t)lib->n_ligands, R = (size_t)p->restarts, K = (size_t)p->top_k;
     w.far = o; o += align256((size_t)lib->n_atoms_total * kFarWords * 8);
-    w.counters = o; o += align256(3 * kNumBins * sizeof(int));
+    w.counters = o; o += align256(kNumCounters * sizeof(int));
     w.bin_list = o; o += align256((size_t)kNumBins * L * sizeof(int));
     w.rscore = o; o += align256(L * R * sizeof(float));
     w.rtrace = o;
@@ -393,8 +406,14 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     }
     if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, g, sa, la, wa, oa, ev, s);
     // launch shapes (occupancy queries stay outside any graph capture)
-    int dock_blocks[kNumBins], final_blocks[kNumBins];
+    int dock_blocks[kNumBins], final_blocks[kNumBins], align_blocks[kNumBins];
     for (int bin = 0; bin < kNumBins; ++bin) {
+        if ((size_t)c->lds_arena < align_lds_min(bin, sa.R))
+            return fail(DOCK_EDEVICE, "device LDS per workgroup too small for the alignment kernel");
+        const std::string a = "a" + std::to_string(bin) + "/" + std::to_string(sa.R) + "/" +
+                              std::to_string(sa.A) + "/" + std::to_string(c->lds_arena);
+        align_blocks[bin] =
+            occupancy(c, a, align_blocks_per_cu(bin, sa.R, sa.A, c->lds_arena)) * c->num_cu;
         const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(kDockWaves) + "/" +
                               std::to_string((sa.T + 63) / 64);
         dock_blocks[bin] = occupancy(c, k, dock_blocks_per_cu(bin, kDockWaves, sa.T)) * c->num_cu;
@@ -408,6 +427,8 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         if (marks) HIP_TRY(hipEventRecord(ev[0], s));
         HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
         if (marks) HIP_TRY(hipEventRecord(ev[1], s));
+        for (int bin = 0; bin < kNumBins; ++bin)
+            HIP_TRY(launch_align(bin, align_blocks[bin], c->lds_arena, g, sa, la, wa, s));
         for (int bin = 0; bin < kNumBins; ++bin)
             HIP_TRY(launch_dock(bin, dock_blocks[bin], kDockWaves, g, sa, la, wa, s));
         if (marks) HIP_TRY(hipEventRecord(ev[2], s));
@@ -453,6 +474,55 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     return DOCK_OK;
 }
 
+// Shell atlas of the alignment kernel: band geometry (pass 1), then the bands
+// that fit one workgroup's LDS, for every type (pass 2).  Grids wider than 256
+// cells in x keep no atlas (every alignment sample reads global memory).
+int build_atlas(dock_ctx *c, Pocket &pk) {
+    GridArgs &g = pk.g;
+    g.atlas = nullptr;
+    g.bands = nullptr;
+    g.blob16 = nullptr;
+    g.nbands = 0;
+    if (g.nx > 256) return DOCK_OK;
+    const size_t ib = (size_t)2 * kMaxBands * sizeof(int4);
+    if (hipMalloc(&pk.d_bands, ib) != hipSuccess) {
+        (void)hipGetLastError();
+        pk.d_bands = nullptr;
+        return fail(DOCK_ENOMEM, "atlas allocation failed");
+    }
+    HIP_TRY(launch_atlas_count(g, pk.d_bands, nullptr));
+    std::vector<int4> info(2 * kMaxBands);
+    HIP_TRY(hipMemcpy(info.data(), pk.d_bands, ib, hipMemcpyDeviceToHost));
+    int nb = 0;
+    long long off = 0;
+    std::vector<int> blob((size_t)g.ntypes * kMaxBands);
+    for (; nb < kMaxBands; ++nb) {
+        const int4 q = info[2 * nb + 1];
+        const long long size16 = q.z / 16 + (long long)q.y;
+        if (q.y < 0 || size16 * 16 > (long long)c->lds_arena) break;
+    }
+    for (int t = 0; t < g.ntypes; ++t)
+        for (int b = 0; b < nb; ++b) {
+            blob[(size_t)t * nb + b] = (int)off;
+            off += info[2 * b + 1].z / 16 + info[2 * b + 1].y;
+        }
+    if (nb == 0 || off >= (1LL << 31)) return DOCK_OK;
+    if (hipMalloc(&pk.d_atlas, (size_t)off * 16) != hipSuccess ||
+        hipMalloc(&pk.d_blob16, (size_t)g.ntypes * nb * sizeof(int)) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DOCK_ENOMEM, "atlas allocation failed");
+    }
+    HIP_TRY(hipMemcpy(pk.d_blob16, blob.data(), (size_t)g.ntypes * nb * sizeof(int),
+                      hipMemcpyHostToDevice));
+    HIP_TRY(launch_atlas_fill(g, pk.d_bands, pk.d_blob16, pk.d_atlas, nb, nullptr));
+    HIP_TRY(hipDeviceSynchronize());
+    g.atlas = pk.d_atlas;
+    g.bands = pk.d_bands;
+    g.blob16 = pk.d_blob16;
+    g.nbands = nb;
+    return DOCK_OK;
+}
+
 }  // namespace
 
 extern "C" {
@@ -474,6 +544,7 @@ int dock_create(int device, dock_ctx **out) {
     if (!c) return fail(DOCK_ENOMEM, "context allocation failed");
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    c->lds_arena = (int)std::min<size_t>(prop.sharedMemPerBlock, (size_t)160 * 1024);
     for (int i = 0; i < kSubmitStreams; ++i) {
         hipStream_t t = nullptr;
         if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
@@ -496,7 +567,7 @@ int dock_destroy(dock_ctx *c) {
         if (kv.second.done) hipEventDestroy(kv.second.done);
         if (kv.second.pinned) hipHostFree(kv.second.pinned);
     }
-    for (auto &kv : c->pockets) hipFree(kv.second.d_cubes);
+    for (auto &kv : c->pockets) kv.second.release();
     for (auto &kv : c->ws) hipFree(kv.second.base);
     for (auto &kv : c->tables) hipFree(kv.second.d);
     for (auto &m : c->marks)
@@ -566,6 +637,14 @@ int dock_pocket_load(dock_ctx *c, const dock_grid_desc *gd, int32_t *pocket_id) 
     g.m2z = (float)(gd->nz - 2);
     g.fnx = (float)gd->nx;
     g.fslab = (float)((long long)gd->nx * gd->ny);
+    g.acx = (g.cx - g.ox) * g.inv_h;
+    g.acy = (g.cy - g.oy) * g.inv_h;
+    g.acz = (g.cz - g.oz) * g.inv_h;
+    const int rc = build_atlas(c, pk);
+    if (rc) {
+        pk.release();
+        return rc;
+    }
     const int32_t id = c->next_pocket++;
     c->pockets[id] = pk;
     *pocket_id = id;
@@ -580,7 +659,7 @@ int dock_pocket_unload(dock_ctx *c, int32_t pocket_id) {
     if (it->second.busy) return fail(DOCK_EBUSY, "pocket has submitted work in flight");
     HIP_TRY(hipSetDevice(c->device));
     HIP_TRY(hipDeviceSynchronize());
-    hipFree(it->second.d_cubes);
+    it->second.release();
     c->pockets.erase(it);
     return DOCK_OK;
 }

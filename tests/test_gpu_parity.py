@@ -75,6 +75,18 @@ def test_ragged_sizes_and_slots(D, ctx):
     check_all(D, pk, lib, q, h, params, label="ragged")
 
 
+def test_alignment_chunks_and_restart_groups(D, ctx):
+    # 40x40 orientations span two lane chunks of the alignment workgroup; 33
+    # restarts leave a one-restart tail group
+    lib = synth.library_uniform(305, 4, (10, 60), (1, 5))
+    pk = synth.pocket_gaussians(305, 4, 48, 0.5, 60, 6.0)
+    q = synth.start_quats(305, 33)
+    print("[case] A=40, R=33", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=32, sweep_passes=1, align_steps=40,
+                          top_k=4, dedup_rmsd=1.0)
+    check_all(D, pk, lib, q, h, params, label="A40")
+
+
 @pytest.mark.parametrize("T", [1, 10, 64, 65, 1024])
 def test_torsion_step_counts(D, ctx, T):
     lib = synth.library_uniform(310 + T, 6, (12, 40), (1, 6))
