@@ -165,6 +165,27 @@ __device__ __forceinline__ float tri_v(const Tri &t, float gx, float gy, float g
     return tri_blend(q0, q1, fx, fy, fz);
 }
 
+// Samples known to lie in [0, n-2] on every axis: the clamps of tri_u are then
+// the identity, floor is truncation and the fraction is exact as v_fract, so
+// this returns the same value with fewer instructions.
+constexpr float kInsideMargin = 0.5f;  // grid cells, far above FP32 rounding of coordinates
+__device__ __forceinline__ float tri_in(const Tri &t, float gx, float gy, float gz, int toff) {
+    const float fx = __builtin_amdgcn_fractf(gx), fy = __builtin_amdgcn_fractf(gy),
+                fz = __builtin_amdgcn_fractf(gz);
+    const uint32_t off = ((uint32_t)fmaf(gz - fz, t.fslab, fmaf(gy - fy, t.fnx, gx - fx))) << 5;
+    const float4 q0 = ldq(t.rs, off, toff);
+    const float4 q1 = ldq(t.rs, off, toff + 16);
+    return tri_blend(q0, q1, fx, fy, fz);
+}
+
+// Whether the ball of radius rad (grid units) about (cx,cy,cz), widened by
+// kInsideMargin, stays inside [0, n-2] on every axis.
+__device__ __forceinline__ bool ball_inside(const Tri &t, float cx, float cy, float cz, float rad) {
+    const float r = rad + kInsideMargin;
+    return cx - r >= 0.0f && cy - r >= 0.0f && cz - r >= 0.0f && cx + r <= t.m2x &&
+           cy + r <= t.m2y && cz + r <= t.m2z;
+}
+
 // Corner cubes from the plain grid (one thread per cell).  Cells at i = nx-1,
 // j = ny-1 or k = nz-1 are never read (the cell corner is at most n-2); they
 // repeat the edge values.
@@ -308,15 +329,23 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
     const int lane = lane_id();
     float cx, cy, cz;
     centroid(Y, n, cx, cy, cz);
+    const float ex = (cx - g.ox) * g.inv_h, ey = (cy - g.oy) * g.inv_h, ez = (cz - g.oz) * g.inv_h;
+    // record: centred grid-unit offset and type offset; all_in: every orientation
+    // of every atom samples inside the grid (spheres about the centroid)
+    bool out_any = false;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const int i = lane + 64 * s;
-        if (i < n)
-            rec[i] = make_float4((Y.x[s] - cx) * g.inv_h, (Y.y[s] - cy) * g.inv_h,
-                                 (Y.z[s] - cz) * g.inv_h, __int_as_float(toff[s]));
+        if (i < n) {
+            const float rx = (Y.x[s] - cx) * g.inv_h, ry = (Y.y[s] - cy) * g.inv_h,
+                        rz = (Y.z[s] - cz) * g.inv_h;
+            out_any = out_any ||
+                      !ball_inside(tr, ex, ey, ez, sqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz))));
+            rec[i] = make_float4(rx, ry, rz, __int_as_float(toff[s]));
+        }
     }
+    const bool all_in = __ballot(out_any) == 0ull;
     wave_lds_sync();
-    const float ex = (cx - g.ox) * g.inv_h, ey = (cy - g.oy) * g.inv_h, ez = (cz - g.oz) * g.inv_h;
     const int NO = sa.A * sa.A;
     u64 best = 0;
     for (int base = sp.first(); base < NO; base += sp.stride()) {
@@ -325,13 +354,24 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
         const int oo = ov ? o : 0;
         const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1], m2 = sa.amat[3 * oo + 2];
         float acc = 0.f;
-        for (int a = 0; a < n; ++a) {
-            const float4 r = rec[a];
-            const int to = uniform_int(__float_as_int(r.w));
-            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
-            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
-            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
-            acc += tri_u(tr, gx, gy, gz, to);
+        if (all_in) {
+            for (int a = 0; a < n; ++a) {
+                const float4 r = rec[a];
+                const int to = uniform_int(__float_as_int(r.w));
+                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
+                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
+                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
+                acc += tri_in(tr, gx, gy, gz, to);
+            }
+        } else {
+            for (int a = 0; a < n; ++a) {
+                const float4 r = rec[a];
+                const int to = uniform_int(__float_as_int(r.w));
+                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
+                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
+                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
+                acc += tri_u(tr, gx, gy, gz, to);
+            }
         }
         const u64 key = ov ? make_key(acc, (uint32_t)o) : 0ull;
         best = key > best ? key : best;
@@ -402,6 +442,25 @@ __device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, int 
 // One torsion decision (Optimize Pose, inner angle loop) for rotatable bond with
 // moving-mask row mrow (NS words), axis atoms (a,b).  cs[c] = (cos,sin) of this
 // lane's candidates k = lane + 64c.  Returns the applied step or kTraceNone.
+// Scores of every candidate of a torsion step on the moving fragment (frames
+// of m moving atoms in rec), added to acc atom by atom.  Inside: every
+// candidate position lies in [0, n-2] on every axis.
+template <int C, bool Inside>
+__device__ __forceinline__ void score_fragment(float (&acc)[C], int m, const float4 *rec,
+                                               const float2 (&cs)[C], const Tri &tr) {
+    for (int q = 0; q < m; ++q) {
+        const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
+        const int to = uniform_int(__float_as_int(r0.w));
+#pragma unroll
+        for (int c = 0; c < C; ++c) {
+            const float gx = fmaf(cs[c].y, r2.x, fmaf(cs[c].x, r1.x, r0.x));
+            const float gy = fmaf(cs[c].y, r2.y, fmaf(cs[c].x, r1.y, r0.y));
+            const float gz = fmaf(cs[c].y, r2.z, fmaf(cs[c].x, r1.z, r0.z));
+            acc[c] += Inside ? tri_in(tr, gx, gy, gz, to) : tri_u(tr, gx, gy, gz, to);
+        }
+    }
+}
+
 template <int NS, int C, class Split>
 __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                               const u64 *far, const int (&toff)[NS], float4 *rec,
@@ -419,6 +478,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
     // moving-atom frames -> LDS (grid units), static atoms -> registers
     float sgx[NS], sgy[NS], sgz[NS];
     bool st[NS];
+    bool out_any = false;  // a moving atom's circle leaves [0, n-2]
     int before = 0;
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
@@ -438,27 +498,24 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                                          (pz - g.oz) * g.inv_h, __int_as_float(toff[s]));
             rec[3 * q + 1] = make_float4(vx * g.inv_h, vy * g.inv_h, vz * g.inv_h,
                                          __int_as_float(i));
+            // every candidate of this atom lies on the circle of radius |V| about P0
+            const bool in = ball_inside(tr, (px - g.ox) * g.inv_h, (py - g.oy) * g.inv_h,
+                                        (pz - g.oz) * g.inv_h,
+                                        sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz))) * g.inv_h);
             rec[3 * q + 2] = make_float4(wx * g.inv_h, wy * g.inv_h, wz * g.inv_h, 0.f);
+            out_any = out_any || !in;
         }
         before += __popcll(mw[s]);
     }
+    const bool all_in = __ballot(out_any) == 0ull;
     wave_lds_sync();
 
     // score every candidate on the moving fragment
     float acc[C];
 #pragma unroll
     for (int c = 0; c < C; ++c) acc[c] = 0.f;
-    for (int q = 0; q < m; ++q) {
-        const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
-        const int to = uniform_int(__float_as_int(r0.w));
-#pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float gx = fmaf(cs[c].y, r2.x, fmaf(cs[c].x, r1.x, r0.x));
-            const float gy = fmaf(cs[c].y, r2.y, fmaf(cs[c].x, r1.y, r0.y));
-            const float gz = fmaf(cs[c].y, r2.z, fmaf(cs[c].x, r1.z, r0.z));
-            acc[c] += tri_u(tr, gx, gy, gz, to);
-        }
-    }
+    if (all_in) score_fragment<C, true>(acc, m, rec, cs, tr);
+    else score_fragment<C, false>(acc, m, rec, cs, tr);
     // Bump Check of every candidate at once.  For moving atom i (frame P0, V, W)
     // and static atom j, the squared distance after a turn by theta is
     //   d2(theta) = Cq + Aq cos(theta) + Bq sin(theta),
@@ -692,12 +749,15 @@ constexpr float kShellPad = 0.0625f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
 constexpr int kShellPrefetch = 4;       // float4 per thread prefetched for the next atom
-constexpr int kShellBatch = 4;          // samples scheduled together
+constexpr int kShellBatch = 2;          // samples scheduled together
 
-// Side entry of a row: bits 0-13 first column (relative to the band's columns),
-// 14-21 first cell x, 22-29 number of cells (0: empty side).
+// Side entry of a row: bits 0-15 first column (relative to the band's columns)
+// minus the first cell x plus kEntryBias, so that cell ix of the segment is
+// column (e & 0xFFFF) - kEntryBias + ix; bits 16-23 first cell x, 24-31 number
+// of cells (0: empty side).
+constexpr int kEntryBias = 512;
 __device__ __forceinline__ int seg_entry(int base, int lo, int len) {
-    return len > 0 ? (base | (lo << 14) | (len << 22)) : 0;
+    return len > 0 ? ((base - lo + kEntryBias) | (lo << 16) | (len << 24)) : kEntryBias;
 }
 
 struct RowShell {
@@ -874,72 +934,98 @@ struct AlignLds {
 };
 
 struct Shell {
-    int y0, z0, thy, thz, rows;
+    int y0, z0, thy, thz, rows, maxcol;
     float cx;             // centre x (grid units): side of a sample
+    unsigned koff, klast; // absolute row index y0*thz + z0 of the first and last rows
+    const int2 *table0;   // table - koff: indexed by the absolute row index
     const int2 *table;    // [thy*thz] (low-side entry, high-side entry)
     const float4 *col;    // corner columns
+    const float4 *zero;   // two zero columns: a miss blends to +0
 };
 
-// Trilinear sample of grid coordinates (gx,gy,gz) from the shell.  Returns false
-// (and leaves v undefined) when the cell is not in the shell.  Clamp = false
-// when every sample of the shell is inside [0, n-2] on each axis, where the
-// clamps of tri_u are the identity.  Same arithmetic as tri_u otherwise.
-template <bool Clamp>
-__device__ __forceinline__ bool shell_sample(const Shell &s, const Tri &t, float gx, float gy,
-                                             float gz, float &v) {
-    float cx = gx, cy = gy, cz = gz, ix, iy, iz;
-    if (Clamp) {
-        cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
-        cy = __builtin_amdgcn_fmed3f(gy, 0.0f, t.my);
-        cz = __builtin_amdgcn_fmed3f(gz, 0.0f, t.mz);
-        ix = floorf(__builtin_amdgcn_fmed3f(gx, 0.0f, t.m2x));
-        iy = floorf(__builtin_amdgcn_fmed3f(gy, 0.0f, t.m2y));
-        iz = floorf(__builtin_amdgcn_fmed3f(gz, 0.0f, t.m2z));
-    } else {
-        ix = floorf(gx);
-        iy = floorf(gy);
-        iz = floorf(gz);
-    }
-    const float fx = cx - ix, fy = cy - iy, fz = cz - iz;
-    const int jy = (int)iy - s.y0, kz = (int)iz - s.z0;
-    const bool rin = (unsigned)jy < (unsigned)s.thy && (unsigned)kz < (unsigned)s.thz;
-    // row index clamped into the table; a row outside it counts as empty
-    const unsigned ri = min((unsigned)(__mul24(jy, s.thz) + kz), (unsigned)s.rows - 1u);
-    const int2 e2 = s.table[ri];
-    const unsigned e = (unsigned)(gx < s.cx ? e2.x : e2.y) & (0u - (unsigned)rin);
-    const int d = (int)ix - (int)((e >> 14) & 255u);
-    const bool hit = (unsigned)d < (e >> 22);
-    const int addr = hit ? (int)(e & 0x3FFFu) + d : 0;
-    const float4 A = s.col[addr], B = s.col[addr + 1];
+__device__ __forceinline__ float lerp_cell(const float4 *p, float fx, float fy, float fz) {
+    const float4 A = p[0], B = p[1];
     const float c00 = fmaf(fx, B.x - A.x, A.x);
     const float c10 = fmaf(fx, B.y - A.y, A.y);
     const float c01 = fmaf(fx, B.z - A.z, A.z);
     const float c11 = fmaf(fx, B.w - A.w, A.w);
     const float c0 = fmaf(fy, c10 - c00, c00);
     const float c1 = fmaf(fy, c11 - c01, c01);
-    v = fmaf(fz, c1 - c0, c0);
-    return hit;
+    return fmaf(fz, c1 - c0, c0);
+}
+
+// Column pair of cell x index ix in row entry pair e2 (side by gx), or the zero
+// pair when the cell is not in the shell.
+__device__ __forceinline__ const float4 *shell_cols(const Shell &s, int2 e2, float gx, int ix,
+                                                    bool &hit) {
+    const unsigned e = (unsigned)(gx < s.cx ? e2.x : e2.y);
+    const int d = ix - (int)((e >> 16) & 255u);
+    hit = (unsigned)d < (e >> 24);
+    return hit ? s.col + ((int)(e & 0xFFFFu) - kEntryBias + ix) : s.zero;
+}
+
+// Trilinear sample of grid coordinates (gx,gy,gz) from the shell; a cell not in
+// the shell gives +0 and hit = false.  Same arithmetic as tri_u.
+//
+// Inside = true: every sample of the shell lies in [0, n-2] on each axis, so the
+// clamps of tri_u are the identity, floor is truncation and the fraction is
+// exact as v_fract.  A sample's distance to the grid centre differs from the
+// atom's radius by FP32 rounding only (~1e-4 cells, against kShellPad), so by
+// construction of the band its row lies in the table and its cell in the row's
+// segment on its side of the centre (two separate segments are more than a cell
+// apart); the row and column indices are only clamped to keep reads in bounds.
+// Inside = false checks the row range and the segment, and reports misses.
+template <bool Inside>
+__device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, float gx, float gy,
+                                              float gz, bool &hit) {
+    if (Inside) {
+        const float fx = __builtin_amdgcn_fractf(gx), fy = __builtin_amdgcn_fractf(gy),
+                    fz = __builtin_amdgcn_fractf(gz);
+        // absolute row iy*thz + iz, clamped to the table's rows [koff, koff+rows)
+        const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz;
+        const unsigned ri = min(max(ra, s.koff), s.klast);
+        const int2 e2 = s.table0[ri];
+        const int e = gx < s.cx ? e2.x : e2.y;
+        // the band holds the sample's cell by construction: no range test, only a
+        // clamp that keeps the read inside the band's columns
+        const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx, s.maxcol);
+        hit = true;
+        return lerp_cell(s.col + c, fx, fy, fz);
+    }
+    const float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
+    const float cy = __builtin_amdgcn_fmed3f(gy, 0.0f, t.my);
+    const float cz = __builtin_amdgcn_fmed3f(gz, 0.0f, t.mz);
+    const float ix = floorf(__builtin_amdgcn_fmed3f(gx, 0.0f, t.m2x));
+    const float iy = floorf(__builtin_amdgcn_fmed3f(gy, 0.0f, t.m2y));
+    const float iz = floorf(__builtin_amdgcn_fmed3f(gz, 0.0f, t.m2z));
+    const int jy = (int)iy - s.y0, kz = (int)iz - s.z0;
+    const bool rin = (unsigned)jy < (unsigned)s.thy && (unsigned)kz < (unsigned)s.thz;
+    const unsigned ri = min((unsigned)(__mul24(jy, s.thz) + kz), (unsigned)s.rows - 1u);
+    int2 e2 = s.table[ri];
+    e2.x &= 0 - (int)rin;
+    e2.y &= 0 - (int)rin;
+    return lerp_cell(shell_cols(s, e2, gx, (int)ix, hit), cx - ix, cy - iy, cz - iz);
 }
 
 // The G samples of one atom (record row ra, centres ectr) for the orientation
 // rows m0..m2, added to acc in restart order.  A sample whose cell is not in the
-// shell adds -0 (the exact identity) and is redone from global memory before
-// any later addition to its accumulator, so every sum keeps atom order.
-template <int G, bool Clamp>
+// shell adds +0 (the exact identity: a sum that starts at +0 never becomes -0)
+// and is redone from global memory before any later addition to its
+// accumulator, so every sum keeps atom order.
+template <int G, bool Inside>
 __device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, const Tri &tr,
                                            const float4 *ra, const float4 *ectr, float4 m0,
                                            float4 m1, float4 m2, int to) {
-    unsigned miss = 0u;
+    bool miss = false;
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) {
         const float4 r = ra[gg], e = ectr[gg];
         const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
         const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
         const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-        float v;
-        const bool hit = shell_sample<Clamp>(sh, tr, gx, gy, gz, v);
-        acc[gg] += hit ? v : -0.0f;
-        miss |= hit ? 0u : (1u << gg);
+        bool hit;
+        acc[gg] += shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
+        miss = miss || !hit;
         // keep the scheduler from hoisting every sample's loads (register spills)
         if ((gg & (kShellBatch - 1)) == kShellBatch - 1) __builtin_amdgcn_sched_barrier(0);
     }
@@ -947,20 +1033,20 @@ __device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, con
     // below and keeps every sample's inputs live)
 #pragma unroll
     for (int gg = 0; gg < G; ++gg) asm volatile("" : "+v"(acc[gg]));
-    if (__ballot(miss != 0u) != 0ull) {
-        // recompute the coordinates rather than keep the first pass's G sets
-        // live across it (an opaque zero offset stops the compiler merging them)
+    if (__ballot(miss) != 0ull) {
+        // recompute rather than keep the first pass's G coordinate sets live
+        // across it (an opaque zero offset stops the compiler merging them)
         int z = 0;
         asm volatile("" : "+v"(z));
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) {
-            if ((miss >> gg) & 1u) {
-                const float4 r = ra[gg + z], e = ectr[gg + z];
-                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-                acc[gg] += tri_u(tr, gx, gy, gz, to);
-            }
+            const float4 r = ra[gg + z], e = ectr[gg + z];
+            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+            bool hit;
+            (void)shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
+            if (!hit) acc[gg] += tri_u(tr, gx, gy, gz, to);
         }
     }
 }
@@ -979,7 +1065,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     float4 *recs = (float4 *)(smem + AlignLds::recs(nmax));
     float4 *ectr = (float4 *)(smem + AlignLds::ectr(nmax, G));
     int4 *ainf = (int4 *)(smem + AlignLds::ainf(nmax, G));  // per atom: band copy, band rows
-    int *misc = (int *)(smem + AlignLds::misc(nmax, G));
+    int *misc = (int *)(smem + AlignLds::misc(nmax, G));  // [0] item, bytes 64..95 zero pair
+    float4 *zero2 = (float4 *)(smem + AlignLds::misc(nmax, G) + 64);
     u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, G));
     float4 *region = (float4 *)(smem + AlignLds::region(nmax, G));
     const int region16 = (arena - (int)AlignLds::region(nmax, G)) / 16;
@@ -987,6 +1074,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     const int groups = (sa.R + G - 1) / G;
     const long long total = (long long)ws.counters[bin] * groups;
     const int NO = sa.A * sa.A;
+    if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (;;) {
         if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
         __syncthreads();
@@ -1031,18 +1119,15 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             const float4 rc = recs[a * G];
             const float rg = sqrtf(fmaf(rc.x, rc.x, fmaf(rc.y, rc.y, rc.z * rc.z)));
             const int b = (int)(rg * (1.0f / kBandWidth));
-            int4 c0 = make_int4(-1, 0, 0, 0), c1 = make_int4(0, 0, 0, 0);
+            // clamps are the identity when the sphere stays inside [0, n-2]
+            const float4 e = ectr[0];
+            const bool inside = ball_inside(tr, e.x, e.y, e.z, rg);
+            int4 c0 = make_int4(-1, 0, 0, 0), c1 = make_int4(0, 0, 0, inside ? 1 : 0);
             if (b < g.nbands) {
                 const int4 gi = g.bands[2 * b], gj = g.bands[2 * b + 1];
                 const int size16 = gj.z / 16 + gj.y;
                 const int t = (int)(lib.type[a0 + a]);
                 if (gj.y >= 0 && size16 <= region16) {
-                    // clamps are the identity when the sphere (half a cell of
-                    // margin) stays inside [0, n-2] on every axis
-                    const float4 e = ectr[0];
-                    const float m = rg + 0.5f;
-                    const bool inside = e.x - m >= 0.0f && e.y - m >= 0.0f && e.z - m >= 0.0f &&
-                                        e.x + m <= g.m2x && e.y + m <= g.m2y && e.z + m <= g.m2z;
                     c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
                     c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
                 }
@@ -1087,10 +1172,24 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     sh.thz = c1.y;
                     sh.rows = c1.x * c1.y;
                     sh.cx = g.acx;
+                    sh.maxcol = c0.y - c1.z - 2;  // last column pair of the band
+                    sh.koff = (unsigned)(c0.z * c1.y + c0.w);
+                    sh.klast = sh.koff + (unsigned)(sh.rows - 1);
                     sh.table = (const int2 *)region;
+                    sh.table0 = sh.table - sh.koff;
                     sh.col = region + c1.z;
-                    if (c1.w) shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
-                    else shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                    sh.zero = zero2;
+                    if (c1.w) shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                    else shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                } else if (c1.w) {
+#pragma unroll
+                    for (int gg = 0; gg < G; ++gg) {
+                        const float4 r = ra[gg], e = ec[gg];
+                        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+                        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+                        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+                        acc[gg] += tri_in(tr, gx, gy, gz, to);
+                    }
                 } else {
 #pragma unroll
                     for (int gg = 0; gg < G; ++gg) {
