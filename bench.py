@@ -29,12 +29,12 @@ sys.path.insert(0, ROOT)
 FLOP_PER_SAMPLE = 49
 PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
 
-# HBM bytes of the docking kernels per step of the default workload, from two
+# HBM bytes of the docking kernels (k_align + k_dock) per step of the default workload, from two
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
 # plain 256 MiB copy read in the same program).  Valid only for the kernel
 # source they were taken on (sha256 prefix below); reported as null otherwise.
-TRAFFIC_SOURCE_SHA = "bc4aeed7d766c5ff"
-TRAFFIC_BYTES_PER_STEP = 8.848679e+11
+TRAFFIC_SOURCE_SHA = "ee947e4d33ad990b"
+TRAFFIC_BYTES_PER_STEP = 3.142574e+11
 
 
 def parse():
@@ -364,7 +364,7 @@ def main():
             "frac": achieved / PEAK_FP32_TFLOPS,
             "traffic": kernel_traffic(a.config, L),
             "traffic_unit": "bytes per step (docking kernels, HBM side of L2)",
-            "kernel": "k_dock (all size bins of one step)",
+            "kernel": "k_align + k_dock (all size bins of one step)",
             "flop_per_step": samples * FLOP_PER_SAMPLE,
             "atom_samples_per_step": samples,
             "dock_ms_per_step": dock_ms,

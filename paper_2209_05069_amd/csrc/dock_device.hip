@@ -740,15 +740,14 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
 // v(i,j,k+1), v(i,j+1,k+1)); cell (i,j,k) is the two consecutive columns i and
 // i+1.  A row table indexed by (j,k) gives each row's cell range on the low-x
 // and the high-x side of the centre.  A workgroup of k_align aligns G restarts
-// of one ligand: per atom it copies that atom's band into LDS (prefetched into
-// registers while the previous atom is sampled), and all G * A * A samples of
-// the atom read LDS.  A sample whose cell is not in the band reads its cube from
+// of one ligand: per atom it copies that atom's band into LDS (coalesced 16-byte
+// loads; the sampling, not the copy, bounds the kernel), and all G * A * A
+// samples of the atom read LDS.  A sample whose cell is not in the band reads its cube from
 // global memory; both give the same eight values, and the transform, blend and
 // atom-order sum are those of align_pose, so the scores are bit-identical.
 constexpr float kShellPad = 0.0625f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
-constexpr int kShellPrefetch = 4;       // float4 per thread prefetched for the next atom
 constexpr int kShellBatch = 2;          // samples scheduled together
 
 // Side entry of a row: bits 0-15 first column (relative to the band's columns)
@@ -1145,7 +1144,6 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             float acc[G];
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) acc[gg] = 0.0f;
-            float4 pf[kShellPrefetch];
             // copy the first atom's band
             {
                 const int4 c0 = ainf[0];
@@ -1155,11 +1153,6 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             __syncthreads();
             for (int a = 0; a < n; ++a) {
                 const int4 cn = a + 1 < n ? ainf[2 * (a + 1)] : make_int4(-1, 0, 0, 0);
-#pragma unroll
-                for (int k = 0; k < kShellPrefetch; ++k) {
-                    const int idx = tid + k * BD;
-                    if (cn.x >= 0 && idx < cn.y) pf[k] = g.atlas[cn.x + idx];
-                }
                 const int to = uniform_int(__float_as_int(xyzt[a].w));
                 const int4 c0 = ainf[2 * a], c1 = ainf[2 * a + 1];
                 const float4 *ra = recs + a * G;
@@ -1201,15 +1194,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     }
                 }
                 __syncthreads();  // every sample of atom a has read the region
-                if (cn.x >= 0) {
-#pragma unroll
-                    for (int k = 0; k < kShellPrefetch; ++k) {
-                        const int idx = tid + k * BD;
-                        if (idx < cn.y) region[idx] = pf[k];
-                    }
-                    for (int k = tid + kShellPrefetch * BD; k < cn.y; k += BD)
-                        region[k] = g.atlas[cn.x + k];
-                }
+                if (cn.x >= 0)  // the next atom's band
+                    for (int k = tid; k < cn.y; k += BD) region[k] = g.atlas[cn.x + k];
                 __syncthreads();
             }
             u64 *slots = (u64 *)region;
