@@ -442,30 +442,63 @@ __device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, int 
 // One torsion decision (Optimize Pose, inner angle loop) for rotatable bond with
 // moving-mask row mrow (NS words), axis atoms (a,b).  cs[c] = (cos,sin) of this
 // lane's candidates k = lane + 64c.  Returns the applied step or kTraceNone.
-// Scores of every candidate of a torsion step on the moving fragment (frames
-// of m moving atoms in rec), added to acc atom by atom.  Inside: every
-// candidate position lies in [0, n-2] on every axis.
-template <int C, bool Inside>
-__device__ __forceinline__ void score_fragment(float (&acc)[C], int m, const float4 *rec,
-                                               const float2 (&cs)[C], const Tri &tr) {
+// Best key (score, candidate) among the nfree bump-free candidates of a torsion
+// step listed in cand, scored on the moving fragment (frames of m moving atoms in
+// rec): lanes take the listed candidates in P passes of 64, each candidate's sum
+// runs over the atoms in order, as when every candidate is scored in place.
+// Inside: every candidate position lies in [0, n-2] on every axis.
+template <int P, bool Inside>
+__device__ __forceinline__ u64 score_free(int nfree, const uint16_t *cand, const float4 *rec,
+                                          int m, const float2 *tors, const Tri &tr) {
+    const int lane = lane_id();
+    int kp[P];
+    float2 csp[P];
+    float acc[P];
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const int idx = lane + 64 * p;
+        kp[p] = cand[idx < nfree ? idx : 0];
+        csp[p] = tors[kp[p]];
+        acc[p] = 0.f;
+    }
     for (int q = 0; q < m; ++q) {
         const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
         const int to = uniform_int(__float_as_int(r0.w));
 #pragma unroll
-        for (int c = 0; c < C; ++c) {
-            const float gx = fmaf(cs[c].y, r2.x, fmaf(cs[c].x, r1.x, r0.x));
-            const float gy = fmaf(cs[c].y, r2.y, fmaf(cs[c].x, r1.y, r0.y));
-            const float gz = fmaf(cs[c].y, r2.z, fmaf(cs[c].x, r1.z, r0.z));
-            acc[c] += Inside ? tri_in(tr, gx, gy, gz, to) : tri_u(tr, gx, gy, gz, to);
+        for (int p = 0; p < P; ++p) {
+            const float gx = fmaf(csp[p].y, r2.x, fmaf(csp[p].x, r1.x, r0.x));
+            const float gy = fmaf(csp[p].y, r2.y, fmaf(csp[p].x, r1.y, r0.y));
+            const float gz = fmaf(csp[p].y, r2.z, fmaf(csp[p].x, r1.z, r0.z));
+            acc[p] += Inside ? tri_in(tr, gx, gy, gz, to) : tri_u(tr, gx, gy, gz, to);
         }
     }
+    u64 best = 0ull;
+#pragma unroll
+    for (int p = 0; p < P; ++p) {
+        const u64 key = lane + 64 * p < nfree ? make_key(acc[p], (uint32_t)kp[p]) : 0ull;
+        best = key > best ? key : best;
+    }
+    return best;
+}
+
+// score_free with the pass count rounded up to a quarter of C (uniform branch).
+template <int C, bool Inside>
+__device__ __forceinline__ u64 score_free_any(int nfree, const uint16_t *cand, const float4 *rec,
+                                              int m, const float2 *tors, const Tri &tr) {
+    constexpr int Q = C >= 4 ? C / 4 : 1;
+    constexpr int P2 = 2 * Q <= C ? 2 * Q : C, P3 = 3 * Q <= C ? 3 * Q : C;
+    const int np = (nfree + 63) >> 6;
+    if (np <= Q) return score_free<Q, Inside>(nfree, cand, rec, m, tors, tr);
+    if (np <= P2) return score_free<P2, Inside>(nfree, cand, rec, m, tors, tr);
+    if (np <= P3) return score_free<P3, Inside>(nfree, cand, rec, m, tors, tr);
+    return score_free<C, Inside>(nfree, cand, rec, m, tors, tr);
 }
 
 template <int NS, int C, class Split>
 __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                               const u64 *far, const int (&toff)[NS], float4 *rec,
-                              const float2 (&cs)[C], const Tri &tr, const GridArgs &g,
-                              const SearchArgs &sa, const Split &sp) {
+                              uint16_t *cand, const float2 (&cs)[C], const Tri &tr,
+                              const GridArgs &g, const SearchArgs &sa, const Split &sp) {
     const int lane = lane_id();
     const Axis A = bond_axis(Y, a, b);
     u64 mw[NS];
@@ -510,12 +543,6 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
     const bool all_in = __ballot(out_any) == 0ull;
     wave_lds_sync();
 
-    // score every candidate on the moving fragment
-    float acc[C];
-#pragma unroll
-    for (int c = 0; c < C; ++c) acc[c] = 0.f;
-    if (all_in) score_fragment<C, true>(acc, m, rec, cs, tr);
-    else score_fragment<C, false>(acc, m, rec, cs, tr);
     // Bump Check of every candidate at once.  For moving atom i (frame P0, V, W)
     // and static atom j, the squared distance after a turn by theta is
     //   d2(theta) = Cq + Aq cos(theta) + Bq sin(theta),
@@ -555,13 +582,25 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
             }
         }
     }
-    u64 best = 0ull;
+    // Only the bump-free candidates are scored (on the paper's workloads more than
+    // half are bumped): list them for this wave, then score the list.
+    int nfree = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int k = sp.first() + lane + sp.stride() * c;
-        const u64 key = (k < sa.T && !bumped[c]) ? make_key(acc[c], (uint32_t)k) : 0ull;
-        best = key > best ? key : best;
+        const bool fr = k < sa.T && !bumped[c];
+        const u64 bm = __ballot(fr);
+        if (fr)
+            cand[nfree + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
+                                                        __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))] =
+                (uint16_t)k;
+        nfree += __popcll(bm);
     }
+    wave_lds_sync();
+    u64 best = 0ull;
+    if (nfree > 0)
+        best = all_in ? score_free_any<C, true>(nfree, cand, rec, m, sa.tors, tr)
+                      : score_free_any<C, false>(nfree, cand, rec, m, sa.tors, tr);
     best = sp.reduce(best);
     const int kstar = best == 0ull ? (int)kTraceNone : (int)key_index(best);
     wave_lds_sync();  // rec is rewritten next
@@ -602,7 +641,12 @@ struct Lds {
         return rot(nmax, nw) + (size_t)kMaxRot * 8;
     }
     static __host__ __device__ size_t rec(int nmax, int nw) { return misc(nmax, nw) + 16; }
-    static __host__ __device__ size_t rec_stride(int nmax) { return (size_t)nmax * 48; }
+    // per wave: moving-atom frames (3 float4 per atom), then the list of
+    // bump-free torsion candidates (u16, up to kMaxTorsionSteps)
+    static __host__ __device__ size_t rec_stride(int nmax) {
+        return (size_t)nmax * 48 + (size_t)kMaxTorsionSteps * 2;
+    }
+    static __host__ __device__ size_t cand(int nmax) { return (size_t)nmax * 48; }
 };
 
 static inline __host__ __device__ int bin_nmax(int bin) { return 32 * (bin + 1); }
@@ -676,6 +720,7 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
     const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
     int *misc = (int *)(smem + Lds::misc(nmax, NS));
     float4 *rec = (float4 *)(smem + Lds::rec(nmax, NS) + (size_t)wave * Lds::rec_stride(nmax));
+    uint16_t *cand = (uint16_t *)((unsigned char *)rec + Lds::cand(nmax));
     const Tri tr = make_tri(g);
 
     float2 cs[C];
@@ -715,8 +760,8 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
                 for (int b = 0; b < B; ++b, ++d) {
                     const int2 ab = rot[b];
                     const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
-                                                        uniform_int(ab.y), far, toff, rec, cs, tr,
-                                                        g, sa, WaveSplit());
+                                                        uniform_int(ab.y), far, toff, rec, cand,
+                                                        cs, tr, g, sa, WaveSplit());
                     if (lane == 0) tr_out[d] = (uint16_t)k;
                 }
             }
@@ -1238,6 +1283,7 @@ __global__ __launch_bounds__(256) void k_plain(GridArgs g, SearchArgs sa, LibArg
     const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
     int *misc = (int *)(smem + Lds::misc(nmax, NS));
     float4 *rec = (float4 *)(smem + Lds::rec(nmax, NS) + (size_t)wave * Lds::rec_stride(nmax));
+    uint16_t *cand = (uint16_t *)((unsigned char *)rec + Lds::cand(nmax));
     u64 *slots = (u64 *)(smem + Lds::rec(nmax, NS) + (size_t)W * Lds::rec_stride(nmax));
     const Tri tr = make_tri(g);
     const BlockSplit sp{wave, W, slots};
@@ -1264,8 +1310,8 @@ __global__ __launch_bounds__(256) void k_plain(GridArgs g, SearchArgs sa, LibArg
         for (int b = 0; b < B; ++b, ++d) {
             const int2 ab = rot[b];
             const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
-                                                uniform_int(ab.y), far, toff, rec, cs, tr, g, sa,
-                                                sp);
+                                                uniform_int(ab.y), far, toff, rec, cand, cs, tr,
+                                                g, sa, sp);
             if (writer) tr_out[d] = (uint16_t)k;
         }
     }

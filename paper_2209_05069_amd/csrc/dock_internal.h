@@ -8,6 +8,7 @@ namespace dockgpu {
 
 constexpr int kMaxAtoms = 256;      // 4 slots of 64 lanes
 constexpr int kMaxRot = 64;
+constexpr int kMaxTorsionSteps = 1024;  // matches DOCK_MAX_TORSION_STEPS
 constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+1)
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
