@@ -201,13 +201,17 @@ int dock_wait(dock_ctx *ctx, uint64_t ticket);
  * call records HIP events on its own stream before its prep kernel, after it,
  * after the docking kernels and after the select/final kernels.
  * dock_get_timing waits for every recorded event, returns the summed
- * milliseconds of each phase and the number of calls since the last
- * dock_get_timing, and starts a new sum. */
+ * milliseconds of each phase, the number of calls and the number of torsion
+ * samples the docking kernels scored since the last dock_get_timing, and starts
+ * a new sum.  A torsion sample is one moving atom of one bump-free candidate
+ * angle: as in Alg. 1 (Optimize Pose), a candidate that fails the Bump Check is
+ * not scored. */
 typedef struct {
     double prep_ms;   /* ligand checks, bump-pair rows, size binning */
     double dock_ms;   /* restarts: start pose, alignment, torsion sweeps */
     double final_ms;  /* pose selection, final rigid step, outputs */
     int64_t calls;
+    int64_t scored_samples;  /* torsion samples scored in the docking phase */
 } dock_timing;
 
 int dock_set_timing(dock_ctx *ctx, int enable);

@@ -498,7 +498,8 @@ template <int NS, int C, class Split>
 __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                               const u64 *far, const int (&toff)[NS], float4 *rec,
                               uint16_t *cand, const float2 (&cs)[C], const Tri &tr,
-                              const GridArgs &g, const SearchArgs &sa, const Split &sp) {
+                              const GridArgs &g, const SearchArgs &sa, const Split &sp,
+                              long long &nscored) {
     const int lane = lane_id();
     const Axis A = bond_axis(Y, a, b);
     u64 mw[NS];
@@ -597,6 +598,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
         nfree += __popcll(bm);
     }
     wave_lds_sync();
+    nscored += (long long)nfree * m;
     u64 best = 0ull;
     if (nfree > 0)
         best = all_in ? score_free_any<C, true>(nfree, cand, rec, m, sa.tors, tr)
@@ -756,15 +758,17 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
             const int o = uniform_int((int)tr_out[0]);
             apply_align(Y, n, o < sa.A * sa.A ? o : 0, sa);
             int d = 1;
+            long long nsc = 0;
             for (int p = 0; p < sa.P; ++p) {
                 for (int b = 0; b < B; ++b, ++d) {
                     const int2 ab = rot[b];
                     const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
                                                         uniform_int(ab.y), far, toff, rec, cand,
-                                                        cs, tr, g, sa, WaveSplit());
+                                                        cs, tr, g, sa, WaveSplit(), nsc);
                     if (lane == 0) tr_out[d] = (uint16_t)k;
                 }
             }
+            if (ws.scored && lane == 0) atomicAdd(ws.scored, (unsigned long long)nsc);
             const float sc = pose_score(Y, n, toff, tr, g);
             if (lane == 0) ws.rscore[(size_t)l * sa.R + r] = sc;
         }
@@ -1306,15 +1310,17 @@ __global__ __launch_bounds__(256) void k_plain(GridArgs g, SearchArgs sa, LibArg
     const int o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, sp);
     if (writer) tr_out[0] = (uint16_t)o;
     int d = 1;
+    long long nsc = 0;  // this wave's share of the scored torsion samples
     for (int p = 0; p < sa.P; ++p) {
         for (int b = 0; b < B; ++b, ++d) {
             const int2 ab = rot[b];
             const int k = torsion_decide<NS, C>(Y, n, mask + b * NS, uniform_int(ab.x),
                                                 uniform_int(ab.y), far, toff, rec, cand, cs, tr,
-                                                g, sa, sp);
+                                                g, sa, sp, nsc);
             if (writer) tr_out[d] = (uint16_t)k;
         }
     }
+    if (ws.scored && lane == 0) atomicAdd(ws.scored, (unsigned long long)nsc);
     const float sc = pose_score(Y, n, toff, tr, g);
     if (writer) ws.rscore[(size_t)l * sa.R + r] = sc;
 }

@@ -67,6 +67,7 @@ struct WorkArgs {
     float *rscore;            // [L][R]
     uint16_t *rtrace;         // [R*(L + P*Nr_total)]
     float *acc_pose;          // [A_total*K*3] kept poses before the final step
+    unsigned long long *scored;  // torsion samples scored (measurement; null: not counted)
 };
 
 struct OutArgs {

@@ -91,6 +91,7 @@ struct dock_ctx {
     int device = 0;
     int num_cu = 0;
     int lds_arena = 0;  // LDS bytes per workgroup of the alignment kernel
+    unsigned long long *d_scored = nullptr;  // scored torsion samples while timing is on
     std::mutex mu;
     std::map<int32_t, Pocket> pockets;
     int32_t next_pocket = 1;
@@ -388,6 +389,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     wa.rscore = (float *)(base + wl.rscore);
     wa.rtrace = user_trace ? o->trace : (uint16_t *)(base + wl.rtrace);
     wa.acc_pose = (float *)(base + wl.acc);
+    wa.scored = c->timing ? c->d_scored : nullptr;
 
     OutArgs oa{};
     oa.best = o->best_score;
@@ -568,6 +570,7 @@ int dock_destroy(dock_ctx *c) {
         if (kv.second.pinned) hipHostFree(kv.second.pinned);
     }
     for (auto &kv : c->pockets) kv.second.release();
+    if (c->d_scored) hipFree(c->d_scored);
     for (auto &kv : c->ws) hipFree(kv.second.base);
     for (auto &kv : c->tables) hipFree(kv.second.d);
     for (auto &m : c->marks)
@@ -857,6 +860,15 @@ int dock_poll(dock_ctx *c, uint64_t ticket, int32_t *done) {
 int dock_set_timing(dock_ctx *c, int enable) {
     if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
     std::lock_guard<std::mutex> lk(c->mu);
+    HIP_TRY(hipSetDevice(c->device));
+    if (enable && !c->d_scored) {
+        if (hipMalloc(&c->d_scored, sizeof(unsigned long long)) != hipSuccess) {
+            c->d_scored = nullptr;
+            (void)hipGetLastError();
+            return fail(DOCK_ENOMEM, "timing counter allocation failed");
+        }
+        HIP_TRY(hipMemset(c->d_scored, 0, sizeof(unsigned long long)));
+    }
     c->timing = enable != 0;
     return DOCK_OK;
 }
@@ -879,6 +891,13 @@ int dock_get_timing(dock_ctx *c, dock_timing *out) {
         for (auto &e : m) (void)hipEventDestroy(e);
     }
     c->marks.clear();
+    if (c->d_scored) {
+        unsigned long long v = 0;
+        HIP_TRY(hipDeviceSynchronize());
+        HIP_TRY(hipMemcpy(&v, c->d_scored, sizeof(v), hipMemcpyDeviceToHost));
+        HIP_TRY(hipMemset(c->d_scored, 0, sizeof(v)));
+        t.scored_samples = (int64_t)v;
+    }
     *out = t;
     return DOCK_OK;
 }

@@ -59,7 +59,8 @@ class Results(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("dock_ms", ctypes.c_double),
-                ("final_ms", ctypes.c_double), ("calls", ctypes.c_int64)]
+                ("final_ms", ctypes.c_double), ("calls", ctypes.c_int64),
+                ("scored_samples", ctypes.c_int64)]
 
 
 EXPORTS = ["dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
@@ -319,7 +320,8 @@ def dock_set_timing(ctx, enable: bool):
 def dock_get_timing(ctx) -> dict:
     t = Timing()
     _check(lib().dock_get_timing(ctx, ctypes.byref(t)))
-    return dict(prep_ms=t.prep_ms, dock_ms=t.dock_ms, final_ms=t.final_ms, calls=t.calls)
+    return dict(prep_ms=t.prep_ms, dock_ms=t.dock_ms, final_ms=t.final_ms, calls=t.calls,
+                scored_samples=t.scored_samples)
 
 
 def trace_offset(l, R, P, rot_off):

@@ -231,6 +231,26 @@ def test_plain_form_matches_batched_form_bitwise(D, ctx):
         check_all(D, pk, lib, q, hp, pparams, label=f"plain-{label}")
 
 
+def test_scored_sample_count(D, ctx):
+    """The torsion samples the kernels report as scored (bump-free candidates x
+    moving atoms) agree between the batched and plain forms (same decisions) and
+    lie between zero and the all-candidates count."""
+    pk, lib, q, s = synth.config(1)
+    counts = {}
+    for label, mode in (("batched", D.DOCK_MODE_BATCHED), ("plain", D.DOCK_MODE_PLAIN)):
+        D.dock_set_timing(ctx, True)
+        D.dock_get_timing(ctx)
+        run_batch(D, ctx, pk, lib, q, mode=mode, **s)
+        tm = D.dock_get_timing(ctx)
+        D.dock_set_timing(ctx, False)
+        counts[label] = tm["scored_samples"]
+    m = [bin(int(w)).count("1") for w in lib.rot_mask.reshape(-1)]
+    all_cand = s["restarts"] * s["sweep_passes"] * s["torsion_steps"] * sum(m)
+    print(f"[scored] {counts} of {all_cand}", flush=True)
+    assert counts["batched"] == counts["plain"]
+    assert 0 < counts["batched"] < all_cand
+
+
 def test_plain_form_flags_invalid_ligands(D, ctx):
     lib = synth.library_uniform(331, 6, (15, 30), (2, 4))
     pk = synth.pocket_gaussians(331, 4, 32, 0.5, 40, 4.0)
