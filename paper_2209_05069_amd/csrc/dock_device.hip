@@ -1348,15 +1348,29 @@ __device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, co
 // ---------------------------------------------------------------------------
 // Select Poses + final rigid step + output, one workgroup per ligand (persistent
 // over the bin list).
-size_t final_lds_bytes(int nmax, int waves, int R, int K) {
+// k_final's shared memory: staged ligand, per-wave alignment records, restart
+// keys and order, selection and output scratch, then (sel_lds) the batch of
+// candidate poses and the kept poses.
+static __host__ __device__ size_t final_sel_offset(int nmax, int waves, int R, int K) {
     const int nw = (nmax + 63) / 64;
-    return Lds::rec(nmax, nw) + (size_t)waves * (size_t)nmax * 16 + (size_t)R * 12 +
-           (size_t)K * 16 + 64;
+    const size_t b = Lds::rec(nmax, nw) + (size_t)waves * (size_t)nmax * 16 + (size_t)R * 12 +
+                     (size_t)K * 16 + 4 + (size_t)(2 * waves + 1) * 4;
+    return (b + 15) & ~(size_t)15;
+}
+
+size_t final_lds_bytes(int nmax, int waves, int R, int K, int sel_lds) {
+    return final_sel_offset(nmax, waves, R, K) +
+           (sel_lds ? (size_t)(waves + K) * (size_t)nmax * 12 : 0);
+}
+
+int final_sel_lds(int nmax, int waves, int R, int K) {
+    return final_lds_bytes(nmax, waves, R, K, 1) <= (size_t)160 * 1024 ? 1 : 0;
 }
 
 template <int NS>
 __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
-                                               WorkArgs ws, OutArgs out, int bin, int single) {
+                                               WorkArgs ws, OutArgs out, int bin, int single,
+                                               int sel_lds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -1375,6 +1389,10 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
     int *fo = (int *)(fsc + K);               // [K]
     int *rank = fo + K;                       // [K]
     int *nsel = rank + K;                     // [1]
+    int *cflag = nsel + 1;                    // [W] candidate conflicts
+    int *kinfo = cflag + W;                   // [1 + W] kept count, slot of each wave's candidate
+    float *candL = (float *)(smem + final_sel_offset(nmax, W, R, K));  // [W][n][3]
+    float *keptL = candL + (size_t)W * nmax * 3;                        // [K][n][3]
     const Tri tr = make_tri(g);
 
     if (single >= 0 && out.status[single] != 0) return;
@@ -1411,7 +1429,91 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
         float *accp = ws.acc_pose + (size_t)a0 * K * 3;
         const uint16_t *trl = ws.rtrace + trace_base(lib, sa, l);
         const int D = 1 + sa.P * B;
-        if (wave == 0) {
+        float *kposes = sel_lds ? keptL : accp;  // kept poses [s][i][3]
+        if (sel_lds) {
+            // Select Poses with every wave: per round, wave w replays the restart
+            // ranked t0 + w and tests it against the poses kept so far (lanes over
+            // kept poses) and against the round's earlier candidates (lanes over
+            // atoms); one thread then takes the round's candidates in rank order,
+            // which is the greedy rule.
+            const float lim = sa.dedup2 * (float)n;
+            int ns = 0;
+            for (int t0 = 0; t0 < R && ns < K; t0 += W) {
+                const int t = t0 + wave;
+                float *cp = candL + (size_t)wave * n * 3;
+                int flag = 1;  // bit 0: conflicts with a kept pose (or no candidate)
+                if (t < R) {
+                    const int r = order[t];
+                    Pose<NS> Y;
+                    replay_pose(Y, xyzt, mask, rot, n, B, r, trl + (size_t)r * D, g, sa);
+#pragma unroll
+                    for (int q = 0; q < NS; ++q) {
+                        const int i = lane + 64 * q;
+                        if (i < n) {
+                            cp[3 * i + 0] = Y.x[q];
+                            cp[3 * i + 1] = Y.y[q];
+                            cp[3 * i + 2] = Y.z[q];
+                        }
+                    }
+                    wave_lds_sync();
+                    bool conflict = false;
+                    if (sa.dedup2 > 0.f && ns > 0) {
+                        const bool ks = lane < ns;
+                        const float *kq = keptL + (size_t)(ks ? lane : 0) * n * 3;
+                        float ssd = 0.f;
+                        for (int i = 0; i < n; ++i) {
+                            const float dx = cp[3 * i + 0] - kq[3 * i + 0];
+                            const float dy = cp[3 * i + 1] - kq[3 * i + 1];
+                            const float dz = cp[3 * i + 2] - kq[3 * i + 2];
+                            ssd = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, ssd)));
+                        }
+                        conflict = __ballot(ks && ssd < lim) != 0ull;
+                    }
+                    flag = conflict ? 1 : 0;
+                }
+                __syncthreads();  // the round's candidates are in LDS
+                if (t < R && sa.dedup2 > 0.f) {
+                    for (int v = 0; v < wave; ++v) {
+                        const float *vp = candL + (size_t)v * n * 3;
+                        float ssd = 0.f;
+#pragma unroll
+                        for (int q = 0; q < NS; ++q) {
+                            const int i = lane + 64 * q;
+                            if (i < n) {
+                                const float dx = cp[3 * i + 0] - vp[3 * i + 0];
+                                const float dy = cp[3 * i + 1] - vp[3 * i + 1];
+                                const float dz = cp[3 * i + 2] - vp[3 * i + 2];
+                                ssd = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, ssd)));
+                            }
+                        }
+                        if (wave_sum(ssd) < lim) flag |= 2 << v;
+                    }
+                }
+                if (lane == 0) cflag[wave] = flag;
+                __syncthreads();
+                if (threadIdx.x == 0) {
+                    int nn = ns, kept = 0;
+                    for (int w = 0; w < W; ++w) {
+                        kinfo[1 + w] = -1;
+                        const int f = cflag[w];
+                        if (nn >= K || (f & 1) || ((f >> 1) & kept)) continue;
+                        kept |= 1 << w;
+                        kinfo[1 + w] = nn;
+                        sel[nn++] = order[t0 + w];
+                    }
+                    kinfo[0] = nn;
+                }
+                __syncthreads();
+                const int slot = kinfo[1 + wave];
+                if (slot >= 0) {
+                    float *kd = keptL + (size_t)slot * n * 3;
+                    for (int e = lane; e < 3 * n; e += 64) kd[e] = cp[e];
+                }
+                ns = kinfo[0];
+                __syncthreads();
+            }
+            if (threadIdx.x == 0) *nsel = ns;
+        } else if (wave == 0) {
             // greedy selection with plain-RMSD dedup; poses rebuilt from traces
             int ns = 0;
             const float lim = sa.dedup2 * (float)n;
@@ -1464,7 +1566,7 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const int i = lane + 64 * q;
-                const float *P = accp + ((size_t)s * n + (i < n ? i : 0)) * 3;
+                const float *P = kposes + ((size_t)s * n + (i < n ? i : 0)) * 3;
                 Y.x[q] = P[0];
                 Y.y[q] = P[1];
                 Y.z[q] = P[2];
@@ -1491,7 +1593,7 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const int i = lane + 64 * q;
-                const float *P = accp + ((size_t)s * n + (i < n ? i : 0)) * 3;
+                const float *P = kposes + ((size_t)s * n + (i < n ? i : 0)) * 3;
                 Y.x[q] = P[0];
                 Y.y[q] = P[1];
                 Y.z[q] = P[2];
@@ -1790,11 +1892,12 @@ template <int NS>
 static hipError_t launch_final_t(int bin, int blocks, int waves, const GridArgs &g,
                                  const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                  const OutArgs &out, int single, hipStream_t s) {
-    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K);
+    const int sel = final_sel_lds(bin_nmax(bin), waves, sa.R, sa.K);
+    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K, sel);
     hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     hipLaunchKernelGGL((k_final<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
-                       bin, single);
+                       bin, single, sel);
     return hipGetLastError();
 }
 
@@ -1919,7 +2022,8 @@ int dock_blocks_per_cu(int bin, int waves, int T) {
 template <int NS>
 static int final_occ(int bin, int waves, int R, int K) {
     int nb = 0;
-    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, R, K);
+    const size_t lds =
+        final_lds_bytes(bin_nmax(bin), waves, R, K, final_sel_lds(bin_nmax(bin), waves, R, K));
     hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_final<NS>, 64 * waves, lds) !=

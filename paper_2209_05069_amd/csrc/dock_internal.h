@@ -84,7 +84,9 @@ struct OutArgs {
 // Shared-memory bytes of the docking kernel for a bin with at most nmax atoms
 // and `waves` wavefronts per workgroup.
 size_t dock_lds_bytes(int nmax, int waves);
-size_t final_lds_bytes(int nmax, int waves, int R, int K);
+size_t final_lds_bytes(int nmax, int waves, int R, int K, int sel_lds);
+// Whether k_final keeps candidate and kept poses in LDS (parallel selection).
+int final_sel_lds(int nmax, int waves, int R, int K);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, int nx, int ny,
