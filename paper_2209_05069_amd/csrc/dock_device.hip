@@ -1105,7 +1105,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, con
 // chunk), each with G score accumulators.
 template <int NS, int G>
 __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                                int bin, int arena) {
+                                                int bin, int arena, int copier) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int BD = blockDim.x, W = BD >> 6, tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
@@ -1122,6 +1122,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     const int groups = (sa.R + G - 1) / G;
     const long long total = (long long)ws.counters[bin] * groups;
     const int NO = sa.A * sa.A;
+    const int Ws = W - copier;  // sampling waves; wave Ws (if any) copies bands
+    const bool sampler = wave < Ws;
     if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (;;) {
         if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
@@ -1175,7 +1177,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                 const int4 gi = g.bands[2 * b], gj = g.bands[2 * b + 1];
                 const int size16 = gj.z / 16 + gj.y;
                 const int t = (int)(lib.type[a0 + a]);
-                if (gj.y >= 0 && size16 <= region16) {
+                if (gj.y >= 0 && band_padded(size16) <= region16) {
                     c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
                     c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
                 }
@@ -1184,68 +1186,92 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             ainf[2 * a + 1] = c1;
         }
         __syncthreads();
-        for (int obase = 0; obase < NO; obase += BD) {
+        for (int obase = 0; obase < NO; obase += Ws * 64) {
             const int o = obase + tid;
-            const bool ov = o < NO;
+            const bool ov = sampler && o < NO;
             const int oo = ov ? o : 0;
             const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1],
                          m2 = sa.amat[3 * oo + 2];
             float acc[G];
 #pragma unroll
             for (int gg = 0; gg < G; ++gg) acc[gg] = 0.0f;
-            // copy the first atom's band
+            // the first atom's band, at the start of the region
+            int offA = 0;
             {
                 const int4 c0 = ainf[0];
-                if (c0.x >= 0)
-                    for (int k = tid; k < c0.y; k += BD) region[k] = g.atlas[c0.x + k];
+                if (c0.x >= 0) {
+                    const int sz = band_padded(c0.y);
+                    for (int k = tid; k < sz; k += BD) region[k] = g.atlas[c0.x + k];
+                }
             }
             __syncthreads();
             for (int a = 0; a < n; ++a) {
                 const int4 cn = a + 1 < n ? ainf[2 * (a + 1)] : make_int4(-1, 0, 0, 0);
                 const int to = uniform_int(__float_as_int(xyzt[a].w));
                 const int4 c0 = ainf[2 * a], c1 = ainf[2 * a + 1];
-                const float4 *ra = recs + a * G;
-                const float4 *ec = ectr;
-                if (c0.x >= 0) {
-                    Shell sh;
-                    sh.y0 = c0.z;
-                    sh.z0 = c0.w;
-                    sh.thy = c1.x;
-                    sh.thz = c1.y;
-                    sh.rows = c1.x * c1.y;
-                    sh.cx = g.acx;
-                    sh.maxcol = c0.y - c1.z - 2;  // last column pair of the band
-                    sh.koff = (unsigned)(c0.z * c1.y + c0.w);
-                    sh.klast = sh.koff + (unsigned)(sh.rows - 1);
-                    sh.table = (const int2 *)region;
-                    sh.table0 = sh.table - sh.koff;
-                    sh.col = region + c1.z;
-                    sh.zero = zero2;
-                    if (c1.w) shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
-                    else shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
-                } else if (c1.w) {
+                // Where the next band goes: when both fit, at the other end of the
+                // region, streamed by the copier wave while this atom is sampled;
+                // else at the start, copied by everyone after the barrier.
+                const int sa_ = c0.x >= 0 ? band_padded(c0.y) : 0;
+                const int sn = cn.x >= 0 ? band_padded(cn.y) : 0;
+                const bool dbl = copier && cn.x >= 0 && sa_ + sn <= region16;
+                const int offN = dbl ? (offA == 0 ? region16 - sn : 0) : 0;
+                if (sampler) {
+                    const float4 *ra = recs + a * G;
+                    const float4 *ec = ectr;
+                    if (c0.x >= 0) {
+                        Shell sh;
+                        sh.y0 = c0.z;
+                        sh.z0 = c0.w;
+                        sh.thy = c1.x;
+                        sh.thz = c1.y;
+                        sh.rows = c1.x * c1.y;
+                        sh.maxcol = c0.y - c1.z - 2;  // last column pair of the band
+                        sh.cx = g.acx;
+                        sh.koff = (unsigned)(c0.z * c1.y + c0.w);
+                        sh.klast = sh.koff + (unsigned)(sh.rows - 1);
+                        sh.table = (const int2 *)(region + offA);
+                        sh.table0 = sh.table - sh.koff;
+                        sh.col = region + offA + c1.z;
+                        sh.zero = zero2;
+                        if (c1.w) shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                        else shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                    } else if (c1.w) {
 #pragma unroll
-                    for (int gg = 0; gg < G; ++gg) {
-                        const float4 r = ra[gg], e = ec[gg];
-                        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-                        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-                        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-                        acc[gg] += tri_in(tr, gx, gy, gz, to);
-                    }
-                } else {
+                        for (int gg = 0; gg < G; ++gg) {
+                            const float4 r = ra[gg], e = ec[gg];
+                            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+                            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+                            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+                            acc[gg] += tri_in(tr, gx, gy, gz, to);
+                        }
+                    } else {
 #pragma unroll
-                    for (int gg = 0; gg < G; ++gg) {
-                        const float4 r = ra[gg], e = ec[gg];
-                        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-                        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-                        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-                        acc[gg] += tri_u(tr, gx, gy, gz, to);
+                        for (int gg = 0; gg < G; ++gg) {
+                            const float4 r = ra[gg], e = ec[gg];
+                            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
+                            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
+                            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+                            acc[gg] += tri_u(tr, gx, gy, gz, to);
+                        }
                     }
+                } else if (dbl) {
+                    // copier wave: global -> LDS loads, 64 float4 per instruction (band
+                    // sizes are padded to whole instructions, so every lane stays in
+                    // the band's slot), then wait for them before the barrier
+                    const float4 *src = g.atlas + cn.x + lane;
+                    for (int c = 0; c < sn; c += 64)
+                        __builtin_amdgcn_global_load_lds(
+                            (const void *)(src + c),
+                            (__attribute__((address_space(3))) void *)(region + offN + c), 16, 0, 0);
+                    __builtin_amdgcn_s_waitcnt(0);
                 }
                 __syncthreads();  // every sample of atom a has read the region
-                if (cn.x >= 0)  // the next atom's band
-                    for (int k = tid; k < cn.y; k += BD) region[k] = g.atlas[cn.x + k];
-                __syncthreads();
+                if (cn.x >= 0 && !dbl) {  // the next atom's band, at the start
+                    for (int k = tid; k < sn; k += BD) region[k] = g.atlas[cn.x + k];
+                    __syncthreads();
+                }
+                offA = offN;
             }
             u64 *slots = (u64 *)region;
 #pragma unroll
@@ -1912,6 +1938,8 @@ hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const
     }
 }
 
+int align_copier(int A);
+
 template <int NS, int G>
 static hipError_t launch_align_t(int bin, int blocks, int waves, int arena,
                                  const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
@@ -1919,7 +1947,7 @@ static hipError_t launch_align_t(int bin, int blocks, int waves, int arena,
     hipFuncSetAttribute((const void *)k_align<NS, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         arena);
     hipLaunchKernelGGL((k_align<NS, G>), dim3(blocks), dim3(64 * waves), (size_t)arena, s, g, sa,
-                       lib, ws, bin, arena);
+                       lib, ws, bin, arena, align_copier(sa.A));
     return hipGetLastError();
 }
 
@@ -1939,9 +1967,14 @@ int align_group(int bin, int R) {
     return G;
 }
 
+// Sampling waves of k_align (lanes over orientations) plus one copier wave that
+// streams the next atom's band into LDS, when the orientations fit 15 waves.
+int align_copier(int A) { return (A * A + 63) / 64 <= 15 ? 1 : 0; }
+
 int align_waves(int A) {
     const int w = (A * A + 63) / 64;
-    return w < 4 ? 4 : (w > 16 ? 16 : w);
+    const int ws = w < 3 ? 3 : (w > 16 ? 16 : w);
+    return ws + align_copier(A);
 }
 
 size_t align_lds_min(int bin, int R) {

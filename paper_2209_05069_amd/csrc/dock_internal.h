@@ -99,6 +99,9 @@ hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const 
 // Shell atlas of a pocket: pass 1 writes the geometry of kMaxBands bands into
 // info[2*kMaxBands]; pass 2 fills nb bands of every type.
 constexpr int kMaxBands = 240;
+// Atlas bands occupy whole 64-float4 blocks (the alignment kernel copies them
+// with one 16-byte load per lane).
+__host__ __device__ inline int band_padded(int size16) { return (size16 + 63) & ~63; }
 hipError_t launch_atlas_count(const GridArgs &g, int4 *info, hipStream_t s);
 hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blob16, float4 *atlas,
                              int nb, hipStream_t s);

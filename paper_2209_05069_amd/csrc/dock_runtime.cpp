@@ -500,13 +500,13 @@ int build_atlas(dock_ctx *c, Pocket &pk) {
     std::vector<int> blob((size_t)g.ntypes * kMaxBands);
     for (; nb < kMaxBands; ++nb) {
         const int4 q = info[2 * nb + 1];
-        const long long size16 = q.z / 16 + (long long)q.y;
+        const long long size16 = band_padded(q.z / 16 + q.y);
         if (q.y < 0 || size16 * 16 > (long long)c->lds_arena) break;
     }
     for (int t = 0; t < g.ntypes; ++t)
         for (int b = 0; b < nb; ++b) {
             blob[(size_t)t * nb + b] = (int)off;
-            off += info[2 * b + 1].z / 16 + info[2 * b + 1].y;
+            off += band_padded(info[2 * b + 1].z / 16 + info[2 * b + 1].y);
         }
     if (nb == 0 || off >= (1LL << 31)) return DOCK_OK;
     if (hipMalloc(&pk.d_atlas, (size_t)off * 16) != hipSuccess ||

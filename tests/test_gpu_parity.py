@@ -87,6 +87,20 @@ def test_alignment_chunks_and_restart_groups(D, ctx):
     check_all(D, pk, lib, q, h, params, label="A40")
 
 
+def test_selection_without_lds_room(D, ctx):
+    # top-64 of 70 restarts on 240-256-atom ligands: the candidate and kept poses
+    # do not fit the final workgroup's LDS, so selection takes the single-wave
+    # path over global memory
+    n = [240, 256]
+    lib = synth.library_from_sizes(306, n, [6, 10])
+    pk = synth.pocket_gaussians(306, 4, 48, 0.5, 60, 6.0)
+    q = synth.start_quats(306, 70)
+    print("[case] K=64 on 256-atom ligands", flush=True)
+    h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=16, sweep_passes=1, align_steps=5,
+                          top_k=64, dedup_rmsd=0.5)
+    check_all(D, pk, lib, q, h, params, label="K64")
+
+
 @pytest.mark.parametrize("T", [1, 10, 64, 65, 1024])
 def test_torsion_step_counts(D, ctx, T):
     lib = synth.library_uniform(310 + T, 6, (12, 40), (1, 6))
