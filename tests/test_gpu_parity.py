@@ -265,6 +265,19 @@ def test_scored_sample_count(D, ctx):
     assert 0 < counts["batched"] < all_cand
 
 
+def test_plain_form_matches_batched_form_bitwise_paper_scale(D, ctx):
+    """On the paper-scale pocket (where the batched alignment reads most samples
+    from the LDS shell bands of the pocket's atlas and the plain form reads every
+    sample from global memory), both forms return identical outputs."""
+    pk, lib, q, s = synth.config(2, n_ligands=150)
+    print("[case] plain vs batched, config 2 pocket, 150 ligands", flush=True)
+    hb, params = run_batch(D, ctx, pk, lib, q, **s)
+    hp, _ = run_batch(D, ctx, pk, lib, q, mode=D.DOCK_MODE_PLAIN, **s)
+    for k in hb:
+        if hb[k] is not None:
+            np.testing.assert_array_equal(hb[k], hp[k], err_msg=f"c2:{k}")
+
+
 def test_plain_form_flags_invalid_ligands(D, ctx):
     lib = synth.library_uniform(331, 6, (15, 30), (2, 4))
     pk = synth.pocket_gaussians(331, 4, 32, 0.5, 40, 4.0)
