@@ -39,26 +39,57 @@ typedef unsigned long long u64;
 // wavefront helpers
 __device__ __forceinline__ int lane_id() { return (int)__lane_id(); }
 
+// Whole-wave reductions with DPP: row_shr 1, 2, 4, 8 leave in lane 15 of every
+// 16-lane row the reduction of its row; row_bcast 15 and 31 carry the rows into
+// lane 63, whose value is then read by every lane.  Lanes outside a shift read 0,
+// the identity of the sum, the max of unsigned keys and the or.  Call with the
+// whole wave active.
+template <int CTRL, int ROWS>
+__device__ __forceinline__ int dpp_read(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xF, true);
+}
+
+template <int CTRL, int ROWS>
+__device__ __forceinline__ u64 dpp_read64(u64 v) {
+    const uint32_t lo = (uint32_t)dpp_read<CTRL, ROWS>((int)(uint32_t)v);
+    const uint32_t hi = (uint32_t)dpp_read<CTRL, ROWS>((int)(uint32_t)(v >> 32));
+    return ((u64)hi << 32) | lo;
+}
+
+__device__ __forceinline__ u64 read_lane64(u64 v, int lane) {
+    const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, lane);
+    const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), lane);
+    return ((u64)hi << 32) | lo;
+}
+
+#define DOCK_DPP_STEPS(STEP) \
+    STEP(0x111, 0xF) STEP(0x112, 0xF) STEP(0x114, 0xF) STEP(0x118, 0xF) STEP(0x142, 0xA) STEP(0x143, 0xC)
+
 __device__ __forceinline__ float wave_sum(float v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
-    return v;
+#define DOCK_SUM_STEP(C, R) v += __int_as_float(dpp_read<C, R>(__float_as_int(v)));
+    DOCK_DPP_STEPS(DOCK_SUM_STEP)
+#undef DOCK_SUM_STEP
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), 63));
 }
 
 __device__ __forceinline__ u64 wave_max_u64(u64 v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        u64 w = __shfl_xor(v, o, 64);
-        v = w > v ? w : v;
+#define DOCK_MAX_STEP(C, R)                 \
+    {                                       \
+        const u64 w = dpp_read64<C, R>(v);  \
+        v = w > v ? w : v;                  \
     }
-    return v;
+    DOCK_DPP_STEPS(DOCK_MAX_STEP)
+#undef DOCK_MAX_STEP
+    return read_lane64(v, 63);
 }
 
 __device__ __forceinline__ u64 wave_or_u64(u64 v) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) v |= __shfl_xor(v, o, 64);
-    return v;
+#define DOCK_OR_STEP(C, R) v |= dpp_read64<C, R>(v);
+    DOCK_DPP_STEPS(DOCK_OR_STEP)
+#undef DOCK_OR_STEP
+    return read_lane64(v, 63);
 }
+#undef DOCK_DPP_STEPS
 
 __device__ __forceinline__ int uniform_int(int v) { return __builtin_amdgcn_readfirstlane(v); }
 
