@@ -19,9 +19,9 @@
 //    remaining pairs against every candidate with two FMAs; one 64-bit key max
 //    (order-preserving score bits, then the lower index) over the bump-free
 //    candidates picks the step;
-//  * grid gathers are raw buffer loads of corner cubes (the 8 corner values of
-//    a cell in one 32-byte record): two 16-byte loads from one cache line per
-//    sample, a 32-bit voffset for the cell and the atom type as scalar offset,
+//  * grid gathers are raw buffer loads of cell cubes (a cell's trilinear
+//    coefficients in one 32-byte record): two 16-byte loads from one cache line
+//    per sample, a 32-bit voffset for the cell and the atom type as scalar offset,
 //    with the range checked by hardware;
 //  * a persistent grid pops (ligand, restart-group) items from a per-bin queue;
 //    the ligand's coordinates, bump-pair rows and masks are staged once per
@@ -122,8 +122,9 @@ __device__ __forceinline__ void wave_lds_sync() {
 // ---------------------------------------------------------------------------
 // Trilinear interpolation.  (gx,gy,gz) are grid coordinates ((p - origin)/h);
 // each is clamped to [0, n-1], the cell corner is min(floor, n-2).  The pocket
-// is stored as corner cubes (see GridArgs): the 8 corners of a cell are one
-// 32-byte record, read as two 16-byte loads from the same cache line.
+// is stored as cell cubes (see GridArgs): the two x-vertex columns of a cell,
+// each as the bilinear coefficients of its (y,z) face, are one 32-byte record,
+// read as two 16-byte loads from the same cache line.
 // toff is the byte offset of the atom type's block.
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
@@ -166,16 +167,17 @@ __device__ __forceinline__ float4 ldq(__amdgpu_buffer_rsrc_t rs, uint32_t voff, 
                        __uint_as_float(v.w));
 }
 
+// Bilinear (y,z) form of one x-vertex column: q = (a, b, c, d) with
+// v(fy,fz) = a + b*fy + c*fz + d*fy*fz.
+__device__ __forceinline__ float col_bilin(const float4 q, float fy, float fz) {
+    return fmaf(fz, fmaf(fy, q.w, q.z), fmaf(fy, q.y, q.x));
+}
+
+// q0, q1: the columns at x vertices i and i+1; the x interpolation comes last.
 __device__ __forceinline__ float tri_blend(const float4 q0, const float4 q1, float fx, float fy,
                                            float fz) {
-    // q = (v(i,j), v(i+1,j), v(i,j+1), v(i+1,j+1)) of slabs k (q0) and k+1 (q1)
-    const float c00 = fmaf(fx, q0.y - q0.x, q0.x);
-    const float c10 = fmaf(fx, q0.w - q0.z, q0.z);
-    const float c01 = fmaf(fx, q1.y - q1.x, q1.x);
-    const float c11 = fmaf(fx, q1.w - q1.z, q1.z);
-    const float c0 = fmaf(fy, c10 - c00, c00);
-    const float c1 = fmaf(fy, c11 - c01, c01);
-    return fmaf(fz, c1 - c0, c0);
+    const float b0 = col_bilin(q0, fy, fz), b1 = col_bilin(q1, fy, fz);
+    return fmaf(fx, b1 - b0, b0);
 }
 
 // wave-uniform type offset (scalar offsets)
@@ -217,7 +219,17 @@ __device__ __forceinline__ bool ball_inside(const Tri &t, float cx, float cy, fl
            cy + r <= t.m2y && cz + r <= t.m2z;
 }
 
-// Corner cubes from the plain grid (one thread per cell).  Cells at i = nx-1,
+// Bilinear coefficients of the (y,z) face at x vertex i of cell (j,k): from
+// its corners v00 = v(i,j,k), v10 = v(i,j+1,k), v01 = v(i,j,k+1),
+// v11 = v(i,j+1,k+1), (a, b, c, d) = (v00, v10 - v00, v01 - v00,
+// (v11 - v10) - (v01 - v00)).
+__device__ __forceinline__ float4 face_coeffs(const float *b0, const float *b1, long long r0,
+                                              long long r1, int i) {
+    const float v00 = b0[r0 + i], v10 = b0[r1 + i], v01 = b1[r0 + i], v11 = b1[r1 + i];
+    return make_float4(v00, v10 - v00, v01 - v00, (v11 - v10) - (v01 - v00));
+}
+
+// Cell cubes from the plain grid (one thread per cell).  Cells at i = nx-1,
 // j = ny-1 or k = nz-1 are never read (the cell corner is at most n-2); they
 // repeat the edge values.
 __global__ void k_build_cubes(const float *__restrict__ v, float4 *__restrict__ q, int ntypes,
@@ -233,10 +245,9 @@ __global__ void k_build_cubes(const float *__restrict__ v, float4 *__restrict__ 
     const int i1 = i + 1 < nx ? i + 1 : i, j1 = j + 1 < ny ? j + 1 : j, k1 = k + 1 < nz ? k + 1 : k;
     const float *b0 = v + t * cells + (long long)k * nx * ny;
     const float *b1 = v + t * cells + (long long)k1 * nx * ny;
-    q[2 * e] = make_float4(b0[(long long)j * nx + i], b0[(long long)j * nx + i1],
-                           b0[(long long)j1 * nx + i], b0[(long long)j1 * nx + i1]);
-    q[2 * e + 1] = make_float4(b1[(long long)j * nx + i], b1[(long long)j * nx + i1],
-                               b1[(long long)j1 * nx + i], b1[(long long)j1 * nx + i1]);
+    const long long r0 = (long long)j * nx, r1 = (long long)j1 * nx;
+    q[2 * e] = face_coeffs(b0, b1, r0, r1, i);
+    q[2 * e + 1] = face_coeffs(b0, b1, r0, r1, i1);
 }
 
 // ---------------------------------------------------------------------------
@@ -815,10 +826,10 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
 // every restart and every ligand.  So the grid cells a sample can fall in
 // depend only on the atom type and that radius.  At pocket load the shell
 // atlas stores, per type and per radius band of kBandWidth cells (thickened by
-// kShellPad on both sides), the cells the band crosses as "corner columns":
-// for vertex x-position i of cell row (j,k) the float4 (v(i,j,k), v(i,j+1,k),
-// v(i,j,k+1), v(i,j+1,k+1)); cell (i,j,k) is the two consecutive columns i and
-// i+1.  A row table indexed by (j,k) gives each row's cell range on the low-x
+// kShellPad on both sides), the cells the band crosses as face columns: for
+// vertex x-position i of cell row (j,k) the bilinear coefficients of the face
+// with corners v(i,j,k), v(i,j+1,k), v(i,j,k+1), v(i,j+1,k+1) (the first half
+// of cube (i,j,k)); cell (i,j,k) is the two consecutive columns i and i+1.  A row table indexed by (j,k) gives each row's cell range on the low-x
 // and the high-x side of the centre.  A workgroup of k_align aligns G restarts
 // of one ligand: per atom it copies that atom's band into LDS (coalesced 16-byte
 // loads; the sampling, not the copy, bounds the kernel), and all G * A * A
@@ -829,6 +840,21 @@ constexpr float kShellPad = 0.0625f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
 constexpr int kShellBatch = 2;          // samples scheduled together
+
+// Of the G restarts a workgroup aligns, align_global_count(G) take their
+// samples from the cubes in global memory (through L1/L2) instead of the LDS
+// band: the value is the same, and the two paths run on separate hardware (the
+// LDS versus the vector-memory pipeline), so their sample rates add.  The
+// global restarts are spread evenly over the G (is_global_restart).
+#ifndef DOCK_ALIGN_GLOBAL_32THS
+#define DOCK_ALIGN_GLOBAL_32THS 8
+#endif
+__host__ __device__ constexpr int align_global_count(int G) {
+    return G * DOCK_ALIGN_GLOBAL_32THS / 32;
+}
+__host__ __device__ constexpr bool is_global_restart(int G, int gg) {
+    return (gg + 1) * align_global_count(G) / G != gg * align_global_count(G) / G;
+}
 
 // Side entry of a row: bits 0-15 first column (relative to the band's columns)
 // minus the first cell x plus kEntryBias, so that cell ix of the segment is
@@ -927,7 +953,7 @@ __global__ __launch_bounds__(1024) void k_atlas_count(GridArgs g, int4 *info) {
 }
 
 // Atlas pass 2 (one workgroup of 1024 per (type, band)): the row table and the
-// corner columns of the band, from the corner cubes.  blob16[t*nb + b] is the
+// face columns of the band, from the cell cubes.  blob16[t*nb + b] is the
 // band's offset in float4 units.
 __global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *info,
                                                      const int *blob16, float4 *atlas, int nb) {
@@ -992,8 +1018,7 @@ __global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *inf
         const int u = v - pre[lo], cn = s.cols_n();
         const int i = u < cn ? s.nlo + u : s.plo + (u - cn);
         const size_t e = ((size_t)t * g.nz * g.ny + (size_t)iz * g.ny + iy) * g.nx + i;
-        const float4 q0 = g.cubes[2 * e], q1 = g.cubes[2 * e + 1];
-        col[v] = make_float4(q0.x, q0.z, q1.x, q1.z);
+        col[v] = g.cubes[2 * e];
     }
 }
 
@@ -1018,19 +1043,12 @@ struct Shell {
     unsigned koff, klast; // absolute row index y0*thz + z0 of the first and last rows
     const int2 *table0;   // table - koff: indexed by the absolute row index
     const int2 *table;    // [thy*thz] (low-side entry, high-side entry)
-    const float4 *col;    // corner columns
+    const float4 *col;    // face columns
     const float4 *zero;   // two zero columns: a miss blends to +0
 };
 
 __device__ __forceinline__ float lerp_cell(const float4 *p, float fx, float fy, float fz) {
-    const float4 A = p[0], B = p[1];
-    const float c00 = fmaf(fx, B.x - A.x, A.x);
-    const float c10 = fmaf(fx, B.y - A.y, A.y);
-    const float c01 = fmaf(fx, B.z - A.z, A.z);
-    const float c11 = fmaf(fx, B.w - A.w, A.w);
-    const float c0 = fmaf(fy, c10 - c00, c00);
-    const float c1 = fmaf(fy, c11 - c01, c01);
-    return fmaf(fz, c1 - c0, c0);
+    return tri_blend(p[0], p[1], fx, fy, fz);
 }
 
 // Column pair of cell x index ix in row entry pair e2 (side by gx), or the zero
@@ -1102,9 +1120,13 @@ __device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, con
         const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
         const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
         const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-        bool hit;
-        acc[gg] += shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
-        miss = miss || !hit;
+        if (is_global_restart(G, gg)) {
+            acc[gg] += Inside ? tri_in(tr, gx, gy, gz, to) : tri_u(tr, gx, gy, gz, to);
+        } else {
+            bool hit;
+            acc[gg] += shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
+            miss = miss || !hit;
+        }
         // keep the scheduler from hoisting every sample's loads (register spills)
         if ((gg & (kShellBatch - 1)) == kShellBatch - 1) __builtin_amdgcn_sched_barrier(0);
     }
@@ -1119,6 +1141,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, con
         asm volatile("" : "+v"(z));
 #pragma unroll
         for (int gg = 0; gg < G; ++gg) {
+            if (is_global_restart(G, gg)) continue;
             const float4 r = ra[gg + z], e = ectr[gg + z];
             const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
             const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));

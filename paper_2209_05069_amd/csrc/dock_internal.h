@@ -14,9 +14,12 @@ constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, final_next, align_next
 
-// The pocket is kept as corner cubes: cube (t,k,j,i) = the grid values of type
-// t at (i,j,k), (i+1,j,k), (i,j+1,k), (i+1,j+1,k), then the same four of slab
-// k+1 (32 bytes), so the 8 corners of a trilinear cell sit in one cache line.
+// The pocket is kept as cell cubes: cube (t,k,j,i) holds, for x = i and then
+// x = i+1, the bilinear coefficients (a, b, c, d) of the (y,z) face with corners
+// v00 = v(x,j,k), v10 = v(x,j+1,k), v01 = v(x,j,k+1), v11 = v(x,j+1,k+1) of
+// type t: a = v00, b = v10 - v00, c = v01 - v00, d = (v11 - v10) - (v01 - v00)
+// (32 bytes), so the trilinear cell sits in one cache line and its value is
+// two bilinear evaluations and one x interpolation.
 struct GridArgs {
     const float4 *cubes;   // [ntypes][nz][ny][nx] cubes, 2 float4 each
     uint32_t ncells;       // ntypes*nx*ny*nz
