@@ -361,6 +361,28 @@ struct BlockSplit {
     }
 };
 
+// Alignment orientation o = i*A + j is R_y(2 pi j / A) R_x(2 pi i / A) about the
+// pose centroid, applied in two stages to the centred grid-unit offset r of an
+// atom.  The x rotation (per atom and i) gives the final y coordinate and the
+// rotated z; the y rotation (per j) the final x and z.  (cos, sin) of 2 pi k / A
+// come from the acs table; e is the centroid in grid units.
+struct XStage {
+    float rx, qz, gy;
+};
+__device__ __forceinline__ XStage align_x(float rx, float ry, float rz, float2 ci, float ey) {
+    XStage s;
+    s.rx = rx;
+    s.qz = fmaf(ci.y, ry, ci.x * rz);
+    s.gy = fmaf(ci.x, ry, fmaf(-ci.y, rz, ey));
+    return s;
+}
+__device__ __forceinline__ float align_gx(const XStage &s, float2 cj, float ex) {
+    return fmaf(cj.x, s.rx, fmaf(cj.y, s.qz, ex));
+}
+__device__ __forceinline__ float align_gz(const XStage &s, float2 cj, float ez) {
+    return fmaf(-cj.y, s.rx, fmaf(cj.x, s.qz, ez));
+}
+
 // Alignment (Rigid Rotation): lanes over the A*A orientations, loop over atoms.
 // rec: per-wave LDS, >= n float4.  toff[s]: type byte offset of this lane's atoms.
 // Applies and returns the best orientation; *best_out = its score.
@@ -394,25 +416,22 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
         const int o = base + lane;
         const bool ov = o < NO;
         const int oo = ov ? o : 0;
-        const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1], m2 = sa.amat[3 * oo + 2];
+        const int oi = oo / sa.A;
+        const float2 ci = sa.acs[oi], cj = sa.acs[oo - oi * sa.A];
         float acc = 0.f;
         if (all_in) {
             for (int a = 0; a < n; ++a) {
                 const float4 r = rec[a];
                 const int to = uniform_int(__float_as_int(r.w));
-                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
-                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
-                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
-                acc += tri_in(tr, gx, gy, gz, to);
+                const XStage xs = align_x(r.x, r.y, r.z, ci, ey);
+                acc += tri_in(tr, align_gx(xs, cj, ex), xs.gy, align_gz(xs, cj, ez), to);
             }
         } else {
             for (int a = 0; a < n; ++a) {
                 const float4 r = rec[a];
                 const int to = uniform_int(__float_as_int(r.w));
-                const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, ex)));
-                const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, ey)));
-                const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, ez)));
-                acc += tri_u(tr, gx, gy, gz, to);
+                const XStage xs = align_x(r.x, r.y, r.z, ci, ey);
+                acc += tri_u(tr, align_gx(xs, cj, ex), xs.gy, align_gz(xs, cj, ez), to);
             }
         }
         const u64 key = ov ? make_key(acc, (uint32_t)o) : 0ull;
@@ -841,18 +860,18 @@ constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
 constexpr int kShellBatch = 2;          // samples scheduled together
 
-// Of the G restarts a workgroup aligns, align_global_count(G) take their
-// samples from the cubes in global memory (through L1/L2) instead of the LDS
-// band: the value is the same, and the two paths run on separate hardware (the
-// LDS versus the vector-memory pipeline), so their sample rates add.  The
-// global restarts are spread evenly over the G (is_global_restart).
+// Of the JM y-rotation slots of a k_align lane, align_global_count(JM) take
+// their samples from the cubes in global memory (through L1/L2) instead of the
+// LDS band: the value is the same, and the two paths run on separate hardware
+// (the LDS versus the vector-memory pipeline), so their sample rates add.  The
+// global slots are spread evenly over the JM (is_global_slot).
 #ifndef DOCK_ALIGN_GLOBAL_32THS
 #define DOCK_ALIGN_GLOBAL_32THS 8
 #endif
 __host__ __device__ constexpr int align_global_count(int G) {
     return G * DOCK_ALIGN_GLOBAL_32THS / 32;
 }
-__host__ __device__ constexpr bool is_global_restart(int G, int gg) {
+__host__ __device__ constexpr bool is_global_slot(int G, int gg) {
     return (gg + 1) * align_global_count(G) / G != gg * align_global_count(G) / G;
 }
 
@@ -1022,18 +1041,20 @@ __global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *inf
     }
 }
 
-// Shared-memory layout of k_align (bytes).
+// Shared-memory layout of k_align (bytes); GR restarts per item, Apad (cos, sin)
+// entries.
 struct AlignLds {
-    static __host__ __device__ size_t xyzt() { return 0; }
-    static __host__ __device__ size_t recs(int nmax) { return (size_t)nmax * 16; }
-    static __host__ __device__ size_t ectr(int nmax, int G) {
-        return recs(nmax) + (size_t)nmax * G * 16;
+    static __host__ __device__ size_t xyzt() { return 0; }                  // [nmax] x,y,z,toff
+    static __host__ __device__ size_t dxyz(int nmax) { return (size_t)nmax * 16; }  // X - c0, toff
+    static __host__ __device__ size_t ectr(int nmax) { return dxyz(nmax) + (size_t)nmax * 16; }
+    static __host__ __device__ size_t ainf(int nmax, int GR) {
+        return ectr(nmax) + (size_t)GR * 32;  // [GR] centroid (world), centroid (grid units)
     }
-    static __host__ __device__ size_t ainf(int nmax, int G) { return ectr(nmax, G) + (size_t)G * 16; }
-    static __host__ __device__ size_t misc(int nmax, int G) { return ainf(nmax, G) + (size_t)nmax * 32; }
-    static __host__ __device__ size_t best(int nmax, int G) { return misc(nmax, G) + 128; }
-    static __host__ __device__ size_t region(int nmax, int G) {
-        return (best(nmax, G) + (size_t)G * 8 + 15) & ~(size_t)15;
+    static __host__ __device__ size_t misc(int nmax, int GR) { return ainf(nmax, GR) + (size_t)nmax * 32; }
+    static __host__ __device__ size_t best(int nmax, int GR) { return misc(nmax, GR) + 128; }
+    static __host__ __device__ size_t acs(int nmax, int GR) { return best(nmax, GR) + (size_t)GR * 8; }
+    static __host__ __device__ size_t region(int nmax, int GR, int Apad) {
+        return (acs(nmax, GR) + (size_t)Apad * 8 + 15) & ~(size_t)15;
     }
 };
 
@@ -1104,81 +1125,91 @@ __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, floa
     return lerp_cell(shell_cols(s, e2, gx, (int)ix, hit), cx - ix, cy - iy, cz - iz);
 }
 
-// The G samples of one atom (record row ra, centres ectr) for the orientation
-// rows m0..m2, added to acc in restart order.  A sample whose cell is not in the
-// shell adds +0 (the exact identity: a sum that starts at +0 never becomes -0)
-// and is redone from global memory before any later addition to its
-// accumulator, so every sum keeps atom order.
-template <int G, bool Inside>
-__device__ __forceinline__ void shell_atom(float (&acc)[G], const Shell &sh, const Tri &tr,
-                                           const float4 *ra, const float4 *ectr, float4 m0,
-                                           float4 m1, float4 m2, int to) {
+// The JM samples of one atom for one lane's strip (restart, x-rotation i, y
+// rotations j0 .. j0+JM-1; cj = the (cos, sin) entries from j0), added to acc in
+// slot order.  Slots from jw on are past A for every lane of the wave and are
+// skipped in whole batches.  A sample whose cell is not in the shell adds +0
+// (the exact identity: a sum that starts at +0 never becomes -0) and is redone
+// from global memory before any later addition to its accumulator, so every sum
+// keeps atom order.
+template <int JM, bool Inside>
+__device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, const Tri &tr,
+                                           const XStage &xs, const float2 *cj, int jw, float ex,
+                                           float ez, int to) {
     bool miss = false;
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) {
-        const float4 r = ra[gg], e = ectr[gg];
-        const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-        const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-        const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-        if (is_global_restart(G, gg)) {
-            acc[gg] += Inside ? tri_in(tr, gx, gy, gz, to) : tri_u(tr, gx, gy, gz, to);
-        } else {
-            bool hit;
-            acc[gg] += shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
-            miss = miss || !hit;
+    for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
+        if (j0 < jw) {
+#pragma unroll
+            for (int jj = j0; jj < j0 + kShellBatch; ++jj) {
+                const float2 c = cj[jj];
+                const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
+                if (is_global_slot(JM, jj)) {
+                    acc[jj] += Inside ? tri_in(tr, gx, xs.gy, gz, to) : tri_u(tr, gx, xs.gy, gz, to);
+                } else {
+                    bool hit;
+                    acc[jj] += shell_sample<Inside>(sh, tr, gx, xs.gy, gz, hit);
+                    miss = miss || !hit;
+                }
+            }
         }
         // keep the scheduler from hoisting every sample's loads (register spills)
-        if ((gg & (kShellBatch - 1)) == kShellBatch - 1) __builtin_amdgcn_sched_barrier(0);
+        __builtin_amdgcn_sched_barrier(0);
     }
     // materialise the sums here (else the compiler defers them past the branch
     // below and keeps every sample's inputs live)
 #pragma unroll
-    for (int gg = 0; gg < G; ++gg) asm volatile("" : "+v"(acc[gg]));
-    if (__ballot(miss) != 0ull) {
-        // recompute rather than keep the first pass's G coordinate sets live
-        // across it (an opaque zero offset stops the compiler merging them)
+    for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
+    if (!Inside && __ballot(miss) != 0ull) {
+        // recompute rather than keep the first pass's coordinates live across it
+        // (an opaque zero offset stops the compiler merging the two passes)
         int z = 0;
         asm volatile("" : "+v"(z));
 #pragma unroll
-        for (int gg = 0; gg < G; ++gg) {
-            if (is_global_restart(G, gg)) continue;
-            const float4 r = ra[gg + z], e = ectr[gg + z];
-            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
+        for (int jj = 0; jj < JM; ++jj) {
+            if (is_global_slot(JM, jj) || jj >= jw) continue;
+            const float2 c = cj[jj + z];
+            const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
             bool hit;
-            (void)shell_sample<Inside>(sh, tr, gx, gy, gz, hit);
-            if (!hit) acc[gg] += tri_u(tr, gx, gy, gz, to);
+            (void)shell_sample<Inside>(sh, tr, gx, xs.gy, gz, hit);
+            if (!hit) acc[jj] += tri_u(tr, gx, xs.gy, gz, to);
         }
     }
 }
 
-// Persistent workgroups pop (ligand, group of G restarts) items of one size bin
+// Persistent workgroups pop (ligand, group of GR restarts) items of one size bin
 // and write each restart's best orientation as the first entry of its decision
-// trace; k_dock then starts from it.  Lanes hold orientations (blockDim.x per
-// chunk), each with G score accumulators.
-template <int NS, int G>
+// trace; k_dock then starts from it.  A lane holds a strip: one restart, one x
+// rotation i and JM consecutive y rotations, with JM score accumulators; strips
+// are ordered (part of the y range, restart, i).  Per atom a lane rebuilds its
+// restart's start-pose offset from the ligand-centred coordinates (the same
+// arithmetic as start_pose), applies the x rotation once and then samples the JM
+// y rotations.  The last wave streams the next atom's band into LDS.
+template <int NS, int JM>
 __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                                int bin, int arena, int copier) {
+                                                int bin, int arena, int GR) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int BD = blockDim.x, W = BD >> 6, tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
+    const int A = sa.A, parts = (A + JM - 1) / JM, Apad = parts * JM;
     float4 *xyzt = (float4 *)(smem + AlignLds::xyzt());
-    float4 *recs = (float4 *)(smem + AlignLds::recs(nmax));
-    float4 *ectr = (float4 *)(smem + AlignLds::ectr(nmax, G));
-    int4 *ainf = (int4 *)(smem + AlignLds::ainf(nmax, G));  // per atom: band copy, band rows
-    int *misc = (int *)(smem + AlignLds::misc(nmax, G));  // [0] item, bytes 64..95 zero pair
-    float4 *zero2 = (float4 *)(smem + AlignLds::misc(nmax, G) + 64);
-    u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, G));
-    float4 *region = (float4 *)(smem + AlignLds::region(nmax, G));
-    const int region16 = (arena - (int)AlignLds::region(nmax, G)) / 16;
+    float4 *dxyz = (float4 *)(smem + AlignLds::dxyz(nmax));
+    float4 *ectr = (float4 *)(smem + AlignLds::ectr(nmax));
+    int4 *ainf = (int4 *)(smem + AlignLds::ainf(nmax, GR));  // per atom: band copy, band rows
+    int *misc = (int *)(smem + AlignLds::misc(nmax, GR));    // [0] item, bytes 64..95 zero pair
+    float4 *zero2 = (float4 *)(smem + AlignLds::misc(nmax, GR) + 64);
+    u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, GR));
+    float2 *acsl = (float2 *)(smem + AlignLds::acs(nmax, GR));
+    float4 *region = (float4 *)(smem + AlignLds::region(nmax, GR, Apad));
+    const int region16 = (arena - (int)AlignLds::region(nmax, GR, Apad)) / 16;
     const Tri tr = make_tri(g);
-    const int groups = (sa.R + G - 1) / G;
+    const int groups = (sa.R + GR - 1) / GR;
     const long long total = (long long)ws.counters[bin] * groups;
-    const int NO = sa.A * sa.A;
-    const int Ws = W - copier;  // sampling waves; wave Ws (if any) copies bands
+    const int Ws = W - 1;  // sampling waves; wave Ws copies bands
     const bool sampler = wave < Ws;
+    const int strips = GR * A * parts;
     if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    for (int k = tid; k < Apad; k += BD) acsl[k] = sa.acs[k];
     for (;;) {
         if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
         __syncthreads();
@@ -1188,67 +1219,91 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
         const int l = ws.bin_list[(size_t)bin * lib.L + li];
         const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
         const int B = lib.rot_off[l + 1] - lib.rot_off[l];
-        const int rbase = grp * G;
+        const int rbase = grp * GR;
         for (int i = tid; i < n; i += BD) {
             const float *p = lib.xyz + 3 * (size_t)(a0 + i);
             const uint32_t toff = (uint32_t)lib.type[a0 + i] * g.type_bytes;
             xyzt[i] = make_float4(p[0], p[1], p[2], __uint_as_float(toff));
         }
-        if (tid < G) bestk[tid] = 0ull;
+        if (tid < GR) bestk[tid] = 0ull;
         __syncthreads();
-        for (int gg = wave; gg < G; gg += W) {
+        if (wave == W - 1) {
+            // ligand-centred coordinates X - c0, with the c0 of start_pose
+            Pose<NS> X;
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q;
+                const float4 v = i < n ? xyzt[i] : make_float4(0.f, 0.f, 0.f, 0.f);
+                X.x[q] = v.x;
+                X.y[q] = v.y;
+                X.z[q] = v.z;
+            }
+            float c0x, c0y, c0z;
+            centroid(X, n, c0x, c0y, c0z);
+#pragma unroll
+            for (int q = 0; q < NS; ++q) {
+                const int i = lane + 64 * q;
+                if (i < n)
+                    dxyz[i] = make_float4(X.x[q] - c0x, X.y[q] - c0y, X.z[q] - c0z, xyzt[i].w);
+            }
+        }
+        for (int gg = wave; gg < GR; gg += W) {
             // restarts past R (last group) repeat the group's first restart
             const int r = rbase + gg < sa.R ? rbase + gg : rbase;
-            {
-                Pose<NS> Y;
-                start_pose(Y, xyzt, n, r, g, sa);
-                float cx, cy, cz;
-                centroid(Y, n, cx, cy, cz);
+            Pose<NS> Y;
+            start_pose(Y, xyzt, n, r, g, sa);
+            float cx, cy, cz;
+            centroid(Y, n, cx, cy, cz);
+            const float ex = (cx - g.ox) * g.inv_h, ey = (cy - g.oy) * g.inv_h,
+                        ez = (cz - g.oz) * g.inv_h;
+            if (lane == 0) {
+                ectr[2 * gg] = make_float4(cx, cy, cz, 0.0f);
+                ectr[2 * gg + 1] = make_float4(ex, ey, ez, 0.0f);
+            }
+            if (gg != 0) continue;
+            // each atom's band in the atlas (radius from the group's first restart)
 #pragma unroll
-                for (int q = 0; q < NS; ++q) {
-                    const int i = lane + 64 * q;
-                    if (i < n)
-                        recs[i * G + gg] = make_float4((Y.x[q] - cx) * g.inv_h,
-                                                       (Y.y[q] - cy) * g.inv_h,
-                                                       (Y.z[q] - cz) * g.inv_h, 0.0f);
+            for (int q = 0; q < NS; ++q) {
+                const int a = lane + 64 * q;
+                if (a >= n) continue;
+                const float rx = (Y.x[q] - cx) * g.inv_h, ry = (Y.y[q] - cy) * g.inv_h,
+                            rz = (Y.z[q] - cz) * g.inv_h;
+                const float rg = sqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz)));
+                const int b = (int)(rg * (1.0f / kBandWidth));
+                // clamps are the identity when the sphere stays inside [0, n-2]
+                const bool inside = ball_inside(tr, ex, ey, ez, rg);
+                int4 c0 = make_int4(-1, 0, 0, 0), c1 = make_int4(0, 0, 0, inside ? 1 : 0);
+                if (b < g.nbands) {
+                    const int4 gi = g.bands[2 * b], gj = g.bands[2 * b + 1];
+                    const int size16 = gj.z / 16 + gj.y;
+                    const int t = (int)(lib.type[a0 + a]);
+                    if (gj.y >= 0 && band_padded(size16) <= region16) {
+                        c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
+                        c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
+                    }
                 }
-                if (lane == 0)
-                    ectr[gg] = make_float4((cx - g.ox) * g.inv_h, (cy - g.oy) * g.inv_h,
-                                           (cz - g.oz) * g.inv_h, 0.0f);
+                ainf[2 * a] = c0;
+                ainf[2 * a + 1] = c1;
             }
         }
         __syncthreads();
-        // each atom's band in the atlas (radius from the group's first restart)
-        for (int a = tid; a < n; a += BD) {
-            const float4 rc = recs[a * G];
-            const float rg = sqrtf(fmaf(rc.x, rc.x, fmaf(rc.y, rc.y, rc.z * rc.z)));
-            const int b = (int)(rg * (1.0f / kBandWidth));
-            // clamps are the identity when the sphere stays inside [0, n-2]
-            const float4 e = ectr[0];
-            const bool inside = ball_inside(tr, e.x, e.y, e.z, rg);
-            int4 c0 = make_int4(-1, 0, 0, 0), c1 = make_int4(0, 0, 0, inside ? 1 : 0);
-            if (b < g.nbands) {
-                const int4 gi = g.bands[2 * b], gj = g.bands[2 * b + 1];
-                const int size16 = gj.z / 16 + gj.y;
-                const int t = (int)(lib.type[a0 + a]);
-                if (gj.y >= 0 && band_padded(size16) <= region16) {
-                    c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
-                    c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
-                }
-            }
-            ainf[2 * a] = c0;
-            ainf[2 * a + 1] = c1;
-        }
-        __syncthreads();
-        for (int obase = 0; obase < NO; obase += Ws * 64) {
-            const int o = obase + tid;
-            const bool ov = sampler && o < NO;
-            const int oo = ov ? o : 0;
-            const float4 m0 = sa.amat[3 * oo + 0], m1 = sa.amat[3 * oo + 1],
-                         m2 = sa.amat[3 * oo + 2];
-            float acc[G];
+        for (int sbase = 0; sbase < strips; sbase += Ws * 64) {
+            const int st = sbase + tid;
+            const bool sv = sampler && st < strips;
+            const int ss = sv ? st : strips - 1;
+            const int part = ss / (GR * A), rem = ss - part * (GR * A);
+            const int gg = rem / A, i = rem - gg * A, j0 = part * JM;
+            // lanes are in strip order, so lane 0 has the wave's lowest j0
+            const bool won = sampler && sbase + 64 * wave < strips;
+            const int jw = min(JM, A - __builtin_amdgcn_readfirstlane(j0));
+            const int r = rbase + gg < sa.R ? rbase + gg : rbase;
+            const float4 m0 = sa.smat[3 * r + 0], m1 = sa.smat[3 * r + 1], m2 = sa.smat[3 * r + 2];
+            const float4 cw = ectr[2 * gg], ce = ectr[2 * gg + 1];
+            const float2 ci = acsl[i];
+            const float2 *cj = acsl + j0;
+            float acc[JM];
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) acc[gg] = 0.0f;
+            for (int jj = 0; jj < JM; ++jj) acc[jj] = 0.0f;
             // the first atom's band, at the start of the region
             int offA = 0;
             {
@@ -1261,18 +1316,23 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             __syncthreads();
             for (int a = 0; a < n; ++a) {
                 const int4 cn = a + 1 < n ? ainf[2 * (a + 1)] : make_int4(-1, 0, 0, 0);
-                const int to = uniform_int(__float_as_int(xyzt[a].w));
                 const int4 c0 = ainf[2 * a], c1 = ainf[2 * a + 1];
                 // Where the next band goes: when both fit, at the other end of the
                 // region, streamed by the copier wave while this atom is sampled;
                 // else at the start, copied by everyone after the barrier.
                 const int sa_ = c0.x >= 0 ? band_padded(c0.y) : 0;
                 const int sn = cn.x >= 0 ? band_padded(cn.y) : 0;
-                const bool dbl = copier && cn.x >= 0 && sa_ + sn <= region16;
+                const bool dbl = cn.x >= 0 && sa_ + sn <= region16;
                 const int offN = dbl ? (offA == 0 ? region16 - sn : 0) : 0;
-                if (sampler) {
-                    const float4 *ra = recs + a * G;
-                    const float4 *ec = ectr;
+                if (won) {
+                    const float4 d = dxyz[a];
+                    const int to = uniform_int(__float_as_int(d.w));
+                    // start-pose offset of this atom for the lane's restart
+                    const float yx = fmaf(m0.x, d.x, fmaf(m0.y, d.y, fmaf(m0.z, d.z, g.cx)));
+                    const float yy = fmaf(m1.x, d.x, fmaf(m1.y, d.y, fmaf(m1.z, d.z, g.cy)));
+                    const float yz = fmaf(m2.x, d.x, fmaf(m2.y, d.y, fmaf(m2.z, d.z, g.cz)));
+                    const XStage xs = align_x((yx - cw.x) * g.inv_h, (yy - cw.y) * g.inv_h,
+                                              (yz - cw.z) * g.inv_h, ci, ce.y);
                     if (c0.x >= 0) {
                         Shell sh;
                         sh.y0 = c0.z;
@@ -1288,28 +1348,26 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.table0 = sh.table - sh.koff;
                         sh.col = region + offA + c1.z;
                         sh.zero = zero2;
-                        if (c1.w) shell_atom<G, true>(acc, sh, tr, ra, ec, m0, m1, m2, to);
-                        else shell_atom<G, false>(acc, sh, tr, ra, ec, m0, m1, m2, to);
+                        if (c1.w) shell_atom<JM, true>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
+                        else shell_atom<JM, false>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
                     } else if (c1.w) {
 #pragma unroll
-                        for (int gg = 0; gg < G; ++gg) {
-                            const float4 r = ra[gg], e = ec[gg];
-                            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-                            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-                            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-                            acc[gg] += tri_in(tr, gx, gy, gz, to);
+                        for (int jj = 0; jj < JM; ++jj) {
+                            if (jj >= jw) break;
+                            const float2 c = cj[jj];
+                            acc[jj] += tri_in(tr, align_gx(xs, c, ce.x), xs.gy,
+                                              align_gz(xs, c, ce.z), to);
                         }
                     } else {
 #pragma unroll
-                        for (int gg = 0; gg < G; ++gg) {
-                            const float4 r = ra[gg], e = ec[gg];
-                            const float gx = fmaf(m0.x, r.x, fmaf(m0.y, r.y, fmaf(m0.z, r.z, e.x)));
-                            const float gy = fmaf(m1.x, r.x, fmaf(m1.y, r.y, fmaf(m1.z, r.z, e.y)));
-                            const float gz = fmaf(m2.x, r.x, fmaf(m2.y, r.y, fmaf(m2.z, r.z, e.z)));
-                            acc[gg] += tri_u(tr, gx, gy, gz, to);
+                        for (int jj = 0; jj < JM; ++jj) {
+                            if (jj >= jw) break;
+                            const float2 c = cj[jj];
+                            acc[jj] += tri_u(tr, align_gx(xs, c, ce.x), xs.gy,
+                                             align_gz(xs, c, ce.z), to);
                         }
                     }
-                } else if (dbl) {
+                } else if (wave == Ws && dbl) {
                     // copier wave: global -> LDS loads, 64 float4 per instruction (band
                     // sizes are padded to whole instructions, so every lane stays in
                     // the band's slot), then wait for them before the barrier
@@ -1327,22 +1385,20 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                 }
                 offA = offN;
             }
-            u64 *slots = (u64 *)region;
+            if (sv) {
+                // best (score, then lowest index) of the strip, into its restart's slot
+                u64 best = 0ull;
 #pragma unroll
-            for (int gg = 0; gg < G; ++gg) {
-                u64 key = ov ? make_key(acc[gg], (uint32_t)o) : 0ull;
-                key = wave_max_u64(key);
-                if (lane == 0) slots[wave * G + gg] = key;
+                for (int jj = 0; jj < JM; ++jj) {
+                    const int j = j0 + jj;
+                    const u64 key = j < A ? make_key(acc[jj], (uint32_t)(i * A + j)) : 0ull;
+                    best = key > best ? key : best;
+                }
+                atomicMax(&bestk[gg], best);
             }
-            __syncthreads();
-            if (tid < G) {
-                u64 b = bestk[tid];
-                for (int w = 0; w < W; ++w) b = slots[w * G + tid] > b ? slots[w * G + tid] : b;
-                bestk[tid] = b;
-            }
-            __syncthreads();
         }
-        if (tid < G && rbase + tid < sa.R) {
+        __syncthreads();
+        if (tid < GR && rbase + tid < sa.R) {
             const int r = rbase + tid;
             ws.rtrace[trace_base(lib, sa, l) + (size_t)r * (1 + sa.P * B)] =
                 (uint16_t)key_index(bestk[tid]);
@@ -1992,86 +2048,70 @@ hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const
     }
 }
 
-int align_copier(int A);
+// k_align geometry: JM = kAlignJ y rotations per lane, the y range in
+// parts = ceil(A / JM) pieces, GR restarts per item so that the GR*A*parts
+// strips fill the 15 sampling waves (at most kAlignMaxGroup, at most R).
+static int align_parts(int A) { return (A + kAlignJ - 1) / kAlignJ; }
 
-template <int NS, int G>
-static hipError_t launch_align_t(int bin, int blocks, int waves, int arena,
-                                 const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
-                                 const WorkArgs &ws, hipStream_t s) {
-    hipFuncSetAttribute((const void *)k_align<NS, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        arena);
-    hipLaunchKernelGGL((k_align<NS, G>), dim3(blocks), dim3(64 * waves), (size_t)arena, s, g, sa,
-                       lib, ws, bin, arena, align_copier(sa.A));
-    return hipGetLastError();
+int align_group(int A, int R) {
+    int GR = (15 * 64) / (A * align_parts(A));
+    if (GR < 1) GR = 1;
+    if (GR > kAlignMaxGroup) GR = kAlignMaxGroup;
+    if (GR > R) GR = R;
+    return GR;
+}
+
+// Sampling waves (enough for the strips, at most 15) plus the copier wave.
+static int align_waves(int A, int R) {
+    const int strips = align_group(A, R) * A * align_parts(A);
+    const int w = (strips + 63) / 64;
+    return (w > 15 ? 15 : w) + 1;
+}
+
+size_t align_lds_min(int bin, int A, int R) {
+    return AlignLds::region(bin_nmax(bin), align_group(A, R), align_parts(A) * kAlignJ) + 1024;
 }
 
 template <int NS>
-static hipError_t launch_align_g(int bin, int G, int blocks, int waves, int arena,
-                                 const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
-                                 const WorkArgs &ws, hipStream_t s) {
-    if (G <= 8) return launch_align_t<NS, 8>(bin, blocks, waves, arena, g, sa, lib, ws, s);
-    if (G <= 16) return launch_align_t<NS, 16>(bin, blocks, waves, arena, g, sa, lib, ws, s);
-    return launch_align_t<NS, 32>(bin, blocks, waves, arena, g, sa, lib, ws, s);
-}
-
-int align_group(int bin, int R) {
-    const int nmax = bin_nmax(bin);
-    int G = nmax <= 64 ? 32 : (nmax <= 128 ? 16 : 8);
-    while (G > 8 && G / 2 >= R) G /= 2;
-    return G;
-}
-
-// Sampling waves of k_align (lanes over orientations) plus one copier wave that
-// streams the next atom's band into LDS, when the orientations fit 15 waves.
-int align_copier(int A) { return (A * A + 63) / 64 <= 15 ? 1 : 0; }
-
-int align_waves(int A) {
-    const int w = (A * A + 63) / 64;
-    const int ws = w < 3 ? 3 : (w > 16 ? 16 : w);
-    return ws + align_copier(A);
-}
-
-size_t align_lds_min(int bin, int R) {
-    return AlignLds::region(bin_nmax(bin), align_group(bin, R)) + 1024;
+static hipError_t launch_align_t(int bin, int blocks, int arena, const GridArgs &g,
+                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                 hipStream_t s) {
+    hipFuncSetAttribute((const void *)k_align<NS, kAlignJ>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, arena);
+    hipLaunchKernelGGL((k_align<NS, kAlignJ>), dim3(blocks), dim3(64 * align_waves(sa.A, sa.R)),
+                       (size_t)arena, s, g, sa, lib, ws, bin, arena, align_group(sa.A, sa.R));
+    return hipGetLastError();
 }
 
 hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                         hipStream_t s) {
-    const int G = align_group(bin, sa.R), waves = align_waves(sa.A);
     switch (bin_slots(bin)) {
-        case 1: return launch_align_g<1>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
-        case 2: return launch_align_g<2>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
-        case 3: return launch_align_g<3>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
-        default: return launch_align_g<4>(bin, G, blocks, waves, arena, g, sa, lib, ws, s);
+        case 1: return launch_align_t<1>(bin, blocks, arena, g, sa, lib, ws, s);
+        case 2: return launch_align_t<2>(bin, blocks, arena, g, sa, lib, ws, s);
+        case 3: return launch_align_t<3>(bin, blocks, arena, g, sa, lib, ws, s);
+        default: return launch_align_t<4>(bin, blocks, arena, g, sa, lib, ws, s);
     }
 }
 
-template <int NS, int G>
+template <int NS>
 static int align_occ_t(int waves, int arena) {
     int nb = 0;
-    hipFuncSetAttribute((const void *)k_align<NS, G>, hipFuncAttributeMaxDynamicSharedMemorySize,
-                        arena);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align<NS, G>, 64 * waves,
+    hipFuncSetAttribute((const void *)k_align<NS, kAlignJ>,
+                        hipFuncAttributeMaxDynamicSharedMemorySize, arena);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_align<NS, kAlignJ>, 64 * waves,
                                                      (size_t)arena) != hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-template <int NS>
-static int align_occ_g(int G, int waves, int arena) {
-    if (G <= 8) return align_occ_t<NS, 8>(waves, arena);
-    if (G <= 16) return align_occ_t<NS, 16>(waves, arena);
-    return align_occ_t<NS, 32>(waves, arena);
-}
-
 int align_blocks_per_cu(int bin, int R, int A, int arena) {
-    const int G = align_group(bin, R), waves = align_waves(A);
+    const int waves = align_waves(A, R);
     switch (bin_slots(bin)) {
-        case 1: return align_occ_g<1>(G, waves, arena);
-        case 2: return align_occ_g<2>(G, waves, arena);
-        case 3: return align_occ_g<3>(G, waves, arena);
-        default: return align_occ_g<4>(G, waves, arena);
+        case 1: return align_occ_t<1>(waves, arena);
+        case 2: return align_occ_t<2>(waves, arena);
+        case 3: return align_occ_t<3>(waves, arena);
+        default: return align_occ_t<4>(waves, arena);
     }
 }
 

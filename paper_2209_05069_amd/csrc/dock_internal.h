@@ -13,6 +13,8 @@ constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, final_next, align_next
+constexpr int kAlignJ = 32;         // k_align: y rotations per lane
+constexpr int kAlignMaxGroup = 64;  // k_align: restarts per item at most
 
 // The pocket is kept as cell cubes: cube (t,k,j,i) holds, for x = i and then
 // x = i+1, the bilinear coefficients (a, b, c, d) of the (y,z) face with corners
@@ -47,6 +49,7 @@ struct SearchArgs {
     float dedup2;          // dedup_rmsd^2, Angstrom^2
     const float4 *smat;    // [R][3] start rotation rows (x,y,z,0)
     const float4 *amat;    // [A*A][3] alignment rotation rows
+    const float2 *acs;     // [ceil(A/kAlignJ)*kAlignJ] (cos, sin) of 2 pi k / A
     const float2 *tors;    // [T] (cos, sin) of 2 pi k / T
 };
 
@@ -114,7 +117,7 @@ hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                         hipStream_t s);
 // Smallest arena k_align accepts for the bin (fixed part plus a minimal region).
-size_t align_lds_min(int bin, int R);
+size_t align_lds_min(int bin, int A, int R);
 int align_blocks_per_cu(int bin, int R, int A, int arena);
 // single >= 0: only that ligand (plain form), else the bin's queue.
 hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,

@@ -70,6 +70,7 @@ struct Tables {
     const float4 *smat = nullptr;
     const float4 *amat = nullptr;
     const float2 *tors = nullptr;
+    const float2 *acs = nullptr;
 };
 
 struct Ticket {
@@ -212,18 +213,28 @@ int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
         const double th = 2.0 * M_PI * k / T;
         tors[k] = make_float2((float)std::cos(th), (float)std::sin(th));
     }
+    // (cos, sin) of 2 pi k / A, padded to whole k_align strips (k >= A wraps)
+    const int nC = (A + kAlignJ - 1) / kAlignJ * kAlignJ;
+    std::vector<float2> acs(nC);
+    for (int k = 0; k < nC; ++k) {
+        const double an = 2.0 * M_PI * k / A;
+        acs[k] = make_float2((float)std::cos(an), (float)std::sin(an));
+    }
     const size_t bS = align256(nS * sizeof(float4)), bA = align256(nA * sizeof(float4)),
-                 bT = align256((size_t)T * sizeof(float2));
+                 bT = align256((size_t)T * sizeof(float2)), bC = align256((size_t)nC * sizeof(float2));
     void *d = nullptr;
-    HIP_TRY(hipMalloc(&d, bS + bA + bT));
+    HIP_TRY(hipMalloc(&d, bS + bA + bT + bC));
     HIP_TRY(hipMemcpy(d, smat.data(), nS * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((char *)d + bS, amat.data(), nA * sizeof(float4), hipMemcpyHostToDevice));
     HIP_TRY(hipMemcpy((char *)d + bS + bA, tors.data(), (size_t)T * sizeof(float2), hipMemcpyHostToDevice));
+    HIP_TRY(hipMemcpy((char *)d + bS + bA + bT, acs.data(), (size_t)nC * sizeof(float2),
+                      hipMemcpyHostToDevice));
     Tables t;
     t.d = d;
     t.smat = (const float4 *)d;
     t.amat = (const float4 *)((char *)d + bS);
     t.tors = (const float2 *)((char *)d + bS + bA);
+    t.acs = (const float2 *)((char *)d + bS + bA + bT);
     c->tables[key] = t;
     *out = t;
     return DOCK_OK;
@@ -366,6 +377,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     sa.smat = tb.smat;
     sa.amat = tb.amat;
     sa.tors = tb.tors;
+    sa.acs = tb.acs;
 
     LibArgs la{};
     la.L = lib->n_ligands;
@@ -410,7 +422,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     // launch shapes (occupancy queries stay outside any graph capture)
     int dock_blocks[kNumBins], final_blocks[kNumBins], align_blocks[kNumBins];
     for (int bin = 0; bin < kNumBins; ++bin) {
-        if ((size_t)c->lds_arena < align_lds_min(bin, sa.R))
+        if ((size_t)c->lds_arena < align_lds_min(bin, sa.A, sa.R))
             return fail(DOCK_EDEVICE, "device LDS per workgroup too small for the alignment kernel");
         const std::string a = "a" + std::to_string(bin) + "/" + std::to_string(sa.R) + "/" +
                               std::to_string(sa.A) + "/" + std::to_string(c->lds_arena);
