@@ -361,6 +361,13 @@ struct BlockSplit {
     }
 };
 
+// Read-only (cos, sin) table in the constant address space: wave-uniform
+// indices load through the scalar cache into SGPRs.
+typedef const __attribute__((address_space(4))) float *cfloat2_p;
+__device__ __forceinline__ float2 ld_cs(cfloat2_p p, int k) {
+    return make_float2(p[2 * k], p[2 * k + 1]);
+}
+
 // Alignment orientation o = i*A + j is R_y(2 pi j / A) R_x(2 pi i / A) about the
 // pose centroid, applied in two stages to the centred grid-unit offset r of an
 // atom.  The x rotation (per atom and i) gives the final y coordinate and the
@@ -858,7 +865,10 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
 constexpr float kShellPad = 0.0625f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
-constexpr int kShellBatch = 2;          // samples scheduled together
+#ifndef DOCK_SHELL_BATCH
+#define DOCK_SHELL_BATCH 2
+#endif
+constexpr int kShellBatch = DOCK_SHELL_BATCH;  // samples scheduled together
 
 // Of the JM y-rotation slots of a k_align lane, align_global_count(JM) take
 // their samples from the cubes in global memory (through L1/L2) instead of the
@@ -866,7 +876,7 @@ constexpr int kShellBatch = 2;          // samples scheduled together
 // (the LDS versus the vector-memory pipeline), so their sample rates add.  The
 // global slots are spread evenly over the JM (is_global_slot).
 #ifndef DOCK_ALIGN_GLOBAL_32THS
-#define DOCK_ALIGN_GLOBAL_32THS 8
+#define DOCK_ALIGN_GLOBAL_32THS 4
 #endif
 __host__ __device__ constexpr int align_global_count(int G) {
     return G * DOCK_ALIGN_GLOBAL_32THS / 32;
@@ -1041,8 +1051,7 @@ __global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *inf
     }
 }
 
-// Shared-memory layout of k_align (bytes); GR restarts per item, Apad (cos, sin)
-// entries.
+// Shared-memory layout of k_align (bytes); GR restarts per item.
 struct AlignLds {
     static __host__ __device__ size_t xyzt() { return 0; }                  // [nmax] x,y,z,toff
     static __host__ __device__ size_t dxyz(int nmax) { return (size_t)nmax * 16; }  // X - c0, toff
@@ -1052,9 +1061,8 @@ struct AlignLds {
     }
     static __host__ __device__ size_t misc(int nmax, int GR) { return ainf(nmax, GR) + (size_t)nmax * 32; }
     static __host__ __device__ size_t best(int nmax, int GR) { return misc(nmax, GR) + 128; }
-    static __host__ __device__ size_t acs(int nmax, int GR) { return best(nmax, GR) + (size_t)GR * 8; }
-    static __host__ __device__ size_t region(int nmax, int GR, int Apad) {
-        return (acs(nmax, GR) + (size_t)Apad * 8 + 15) & ~(size_t)15;
+    static __host__ __device__ size_t region(int nmax, int GR) {
+        return (best(nmax, GR) + (size_t)GR * 8 + 15) & ~(size_t)15;
     }
 };
 
@@ -1125,6 +1133,51 @@ __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, floa
     return lerp_cell(shell_cols(s, e2, gx, (int)ix, hit), cx - ix, cy - iy, cz - iz);
 }
 
+// One batch of kShellBatch samples (y slots j0..) of a sphere inside the grid,
+// in phases so that a wave keeps every sample's reads in flight together:
+// fractions and row entries, then the cell columns (LDS band, or the cube in
+// global memory for the slots is_global_slot picks), then the blends.  Each
+// value is the one shell_sample<true> or tri_in gives.
+template <int JM>
+__device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, const Shell &s,
+                                               const Tri &t, const float (&gx)[kShellBatch],
+                                               float gy, const float (&gz)[kShellBatch], int to) {
+    const float fy = __builtin_amdgcn_fractf(gy);
+    float fx[kShellBatch], fz[kShellBatch];
+    uint32_t off[kShellBatch];
+    int2 e2[kShellBatch];
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) {
+        fx[k] = __builtin_amdgcn_fractf(gx[k]);
+        fz[k] = __builtin_amdgcn_fractf(gz[k]);
+        if (is_global_slot(JM, j0 + k)) {
+            off[k] = ((uint32_t)fmaf(gz[k] - fz[k], t.fslab, fmaf(gy - fy, t.fnx, gx[k] - fx[k])))
+                     << 5;
+        } else {
+            // absolute row iy*thz + iz, clamped to the table's rows
+            const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz[k];
+            e2[k] = s.table0[min(max(ra, s.koff), s.klast)];
+        }
+    }
+    float4 q0[kShellBatch], q1[kShellBatch];
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) {
+        if (is_global_slot(JM, j0 + k)) {
+            q0[k] = ldq(t.rs, off[k], to);
+            q1[k] = ldq(t.rs, off[k], to + 16);
+        } else {
+            const int e = gx[k] < s.cx ? e2[k].x : e2[k].y;
+            const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx[k], s.maxcol);
+            q0[k] = s.col[c];
+            q1[k] = s.col[c + 1];
+        }
+    }
+    // every column read is issued before the first blend waits for one
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) v[k] = tri_blend(q0[k], q1[k], fx[k], fy, fz[k]);
+}
+
 // The JM samples of one atom for one lane's strip (restart, x-rotation i, y
 // rotations j0 .. j0+JM-1; cj = the (cos, sin) entries from j0), added to acc in
 // slot order.  Slots from jw on are past A for every lane of the wave and are
@@ -1134,15 +1187,36 @@ __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, floa
 // keeps atom order.
 template <int JM, bool Inside>
 __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, const Tri &tr,
-                                           const XStage &xs, const float2 *cj, int jw, float ex,
+                                           const XStage &xs, cfloat2_p cj, int jw, float ex,
                                            float ez, int to) {
+    if (Inside) {
+#pragma unroll
+        for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
+            if (j0 < jw) {
+                float gx[kShellBatch], gz[kShellBatch], v[kShellBatch];
+#pragma unroll
+                for (int k = 0; k < kShellBatch; ++k) {
+                    const float2 c = ld_cs(cj, j0 + k);
+                    gx[k] = align_gx(xs, c, ex);
+                    gz[k] = align_gz(xs, c, ez);
+                }
+                shell_batch_in<JM>(v, j0, sh, tr, gx, xs.gy, gz, to);
+#pragma unroll
+                for (int k = 0; k < kShellBatch; ++k) acc[j0 + k] += v[k];
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+#pragma unroll
+        for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
+        return;
+    }
     bool miss = false;
 #pragma unroll
     for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
         if (j0 < jw) {
 #pragma unroll
             for (int jj = j0; jj < j0 + kShellBatch; ++jj) {
-                const float2 c = cj[jj];
+                const float2 c = ld_cs(cj, jj);
                 const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
                 if (is_global_slot(JM, jj)) {
                     acc[jj] += Inside ? tri_in(tr, gx, xs.gy, gz, to) : tri_u(tr, gx, xs.gy, gz, to);
@@ -1168,7 +1242,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
 #pragma unroll
         for (int jj = 0; jj < JM; ++jj) {
             if (is_global_slot(JM, jj) || jj >= jw) continue;
-            const float2 c = cj[jj + z];
+            const float2 c = ld_cs(cj, jj + z);
             const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
             bool hit;
             (void)shell_sample<Inside>(sh, tr, gx, xs.gy, gz, hit);
@@ -1191,7 +1265,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int BD = blockDim.x, W = BD >> 6, tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
-    const int A = sa.A, parts = (A + JM - 1) / JM, Apad = parts * JM;
+    const int A = sa.A, parts = (A + JM - 1) / JM;
     float4 *xyzt = (float4 *)(smem + AlignLds::xyzt());
     float4 *dxyz = (float4 *)(smem + AlignLds::dxyz(nmax));
     float4 *ectr = (float4 *)(smem + AlignLds::ectr(nmax));
@@ -1199,17 +1273,16 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     int *misc = (int *)(smem + AlignLds::misc(nmax, GR));    // [0] item, bytes 64..95 zero pair
     float4 *zero2 = (float4 *)(smem + AlignLds::misc(nmax, GR) + 64);
     u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, GR));
-    float2 *acsl = (float2 *)(smem + AlignLds::acs(nmax, GR));
-    float4 *region = (float4 *)(smem + AlignLds::region(nmax, GR, Apad));
-    const int region16 = (arena - (int)AlignLds::region(nmax, GR, Apad)) / 16;
+    float4 *region = (float4 *)(smem + AlignLds::region(nmax, GR));
+    const int region16 = (arena - (int)AlignLds::region(nmax, GR)) / 16;
     const Tri tr = make_tri(g);
     const int groups = (sa.R + GR - 1) / GR;
     const long long total = (long long)ws.counters[bin] * groups;
     const int Ws = W - 1;  // sampling waves; wave Ws copies bands
     const bool sampler = wave < Ws;
-    const int strips = GR * A * parts;
+    // strips of one part padded to whole waves, so that j0 is wave-uniform
+    const int spp = (GR * A + 63) & ~63, strips = parts * spp;
     if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
-    for (int k = tid; k < Apad; k += BD) acsl[k] = sa.acs[k];
     for (;;) {
         if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
         __syncthreads();
@@ -1288,19 +1361,18 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
         }
         __syncthreads();
         for (int sbase = 0; sbase < strips; sbase += Ws * 64) {
-            const int st = sbase + tid;
-            const bool sv = sampler && st < strips;
-            const int ss = sv ? st : strips - 1;
-            const int part = ss / (GR * A), rem = ss - part * (GR * A);
-            const int gg = rem / A, i = rem - gg * A, j0 = part * JM;
-            // lanes are in strip order, so lane 0 has the wave's lowest j0
-            const bool won = sampler && sbase + 64 * wave < strips;
-            const int jw = min(JM, A - __builtin_amdgcn_readfirstlane(j0));
+            const int wbase = __builtin_amdgcn_readfirstlane(sbase + 64 * wave);
+            const int part = wbase / spp, rem = sbase + tid - part * spp;
+            const bool sv = sampler && wbase < strips && rem < GR * A;
+            const int rr = sv ? rem : 0;  // padding lanes repeat the part's first strip
+            const int gg = rr / A, i = rr - gg * A, j0 = part * JM;
+            const bool won = sampler && wbase < strips;
+            const int jw = min(JM, A - j0);
             const int r = rbase + gg < sa.R ? rbase + gg : rbase;
             const float4 m0 = sa.smat[3 * r + 0], m1 = sa.smat[3 * r + 1], m2 = sa.smat[3 * r + 2];
             const float4 cw = ectr[2 * gg], ce = ectr[2 * gg + 1];
-            const float2 ci = acsl[i];
-            const float2 *cj = acsl + j0;
+            const float2 ci = sa.acs[i];
+            const cfloat2_p cj = (cfloat2_p)sa.acs + 2 * j0;
             float acc[JM];
 #pragma unroll
             for (int jj = 0; jj < JM; ++jj) acc[jj] = 0.0f;
@@ -1354,7 +1426,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
 #pragma unroll
                         for (int jj = 0; jj < JM; ++jj) {
                             if (jj >= jw) break;
-                            const float2 c = cj[jj];
+                            const float2 c = ld_cs(cj, jj);
                             acc[jj] += tri_in(tr, align_gx(xs, c, ce.x), xs.gy,
                                               align_gz(xs, c, ce.z), to);
                         }
@@ -1362,7 +1434,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
 #pragma unroll
                         for (int jj = 0; jj < JM; ++jj) {
                             if (jj >= jw) break;
-                            const float2 c = cj[jj];
+                            const float2 c = ld_cs(cj, jj);
                             acc[jj] += tri_u(tr, align_gx(xs, c, ce.x), xs.gy,
                                              align_gz(xs, c, ce.z), to);
                         }
@@ -2049,27 +2121,27 @@ hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const
 }
 
 // k_align geometry: JM = kAlignJ y rotations per lane, the y range in
-// parts = ceil(A / JM) pieces, GR restarts per item so that the GR*A*parts
-// strips fill the 15 sampling waves (at most kAlignMaxGroup, at most R).
+// parts = ceil(A / JM) pieces, GR restarts per item so that the parts, each of
+// GR*A strips padded to whole waves, fill the 15 sampling waves (GR at most
+// kAlignMaxGroup and R, at least 1).
 static int align_parts(int A) { return (A + kAlignJ - 1) / kAlignJ; }
 
 int align_group(int A, int R) {
-    int GR = (15 * 64) / (A * align_parts(A));
-    if (GR < 1) GR = 1;
-    if (GR > kAlignMaxGroup) GR = kAlignMaxGroup;
-    if (GR > R) GR = R;
+    const int parts = align_parts(A);
+    int GR = 1;
+    while (GR < kAlignMaxGroup && GR < R && parts * (((GR + 1) * A + 63) & ~63) <= 15 * 64) ++GR;
     return GR;
 }
 
 // Sampling waves (enough for the strips, at most 15) plus the copier wave.
 static int align_waves(int A, int R) {
-    const int strips = align_group(A, R) * A * align_parts(A);
-    const int w = (strips + 63) / 64;
+    const int strips = align_parts(A) * ((align_group(A, R) * A + 63) & ~63);
+    const int w = strips / 64;
     return (w > 15 ? 15 : w) + 1;
 }
 
 size_t align_lds_min(int bin, int A, int R) {
-    return AlignLds::region(bin_nmax(bin), align_group(A, R), align_parts(A) * kAlignJ) + 1024;
+    return AlignLds::region(bin_nmax(bin), align_group(A, R)) + 1024;
 }
 
 template <int NS>
