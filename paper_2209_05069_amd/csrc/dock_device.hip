@@ -131,6 +131,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 struct Tri {
     __amdgpu_buffer_rsrc_t rs;
     float mx, my, mz, m2x, m2y, m2z, fnx, fslab;
+    uint32_t nx, slab;  // cells per row and per slab
 };
 
 __device__ __forceinline__ Tri make_tri(const GridArgs &g) {
@@ -140,6 +141,8 @@ __device__ __forceinline__ Tri make_tri(const GridArgs &g) {
     t.mx = g.mx; t.my = g.my; t.mz = g.mz;
     t.m2x = g.m2x; t.m2y = g.m2y; t.m2z = g.m2z;
     t.fnx = g.fnx; t.fslab = g.fslab;
+    t.nx = (uint32_t)g.nx;
+    t.slab = (uint32_t)g.nx * (uint32_t)g.ny;
     return t;
 }
 
@@ -201,11 +204,16 @@ __device__ __forceinline__ float tri_v(const Tri &t, float gx, float gy, float g
 // Samples known to lie in [0, n-2] on every axis: the clamps of tri_u are then
 // the identity, floor is truncation and the fraction is exact as v_fract, so
 // this returns the same value with fewer instructions.
+// Byte offset of the cube of a sample in [0, n-2] on every axis: truncation is
+// floor there, and cell indices and sizes fit the 24-bit multipliers.
+__device__ __forceinline__ uint32_t in_cell(const Tri &t, float gx, float gy, float gz) {
+    return (__umul24((uint32_t)gz, t.slab) + __umul24((uint32_t)gy, t.nx) + (uint32_t)gx) << 5;
+}
 constexpr float kInsideMargin = 0.5f;  // grid cells, far above FP32 rounding of coordinates
 __device__ __forceinline__ float tri_in(const Tri &t, float gx, float gy, float gz, int toff) {
     const float fx = __builtin_amdgcn_fractf(gx), fy = __builtin_amdgcn_fractf(gy),
                 fz = __builtin_amdgcn_fractf(gz);
-    const uint32_t off = ((uint32_t)fmaf(gz - fz, t.fslab, fmaf(gy - fy, t.fnx, gx - fx))) << 5;
+    const uint32_t off = in_cell(t, gx, gy, gz);
     const float4 q0 = ldq(t.rs, off, toff);
     const float4 q1 = ldq(t.rs, off, toff + 16);
     return tri_blend(q0, q1, fx, fy, fz);
@@ -876,7 +884,7 @@ constexpr int kShellBatch = DOCK_SHELL_BATCH;  // samples scheduled together
 // (the LDS versus the vector-memory pipeline), so their sample rates add.  The
 // global slots are spread evenly over the JM (is_global_slot).
 #ifndef DOCK_ALIGN_GLOBAL_32THS
-#define DOCK_ALIGN_GLOBAL_32THS 4
+#define DOCK_ALIGN_GLOBAL_32THS 0
 #endif
 __host__ __device__ constexpr int align_global_count(int G) {
     return G * DOCK_ALIGN_GLOBAL_32THS / 32;
@@ -1151,8 +1159,7 @@ __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, 
         fx[k] = __builtin_amdgcn_fractf(gx[k]);
         fz[k] = __builtin_amdgcn_fractf(gz[k]);
         if (is_global_slot(JM, j0 + k)) {
-            off[k] = ((uint32_t)fmaf(gz[k] - fz[k], t.fslab, fmaf(gy - fy, t.fnx, gx[k] - fx[k])))
-                     << 5;
+            off[k] = in_cell(t, gx[k], gy, gz[k]);
         } else {
             // absolute row iy*thz + iz, clamped to the table's rows
             const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz[k];
