@@ -76,15 +76,30 @@ def test_ragged_sizes_and_slots(D, ctx):
 
 
 def test_alignment_chunks_and_restart_groups(D, ctx):
-    # 40x40 orientations span two lane chunks of the alignment workgroup; 33
+    # A = 40 splits the 40 y rotations of a lane strip into two parts (32 + 8),
+    # each padded to whole waves: 11 restarts per alignment group, so 34
     # restarts leave a one-restart tail group
     lib = synth.library_uniform(305, 4, (10, 60), (1, 5))
     pk = synth.pocket_gaussians(305, 4, 48, 0.5, 60, 6.0)
-    q = synth.start_quats(305, 33)
-    print("[case] A=40, R=33", flush=True)
+    q = synth.start_quats(305, 34)
+    print("[case] A=40, R=34", flush=True)
     h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=32, sweep_passes=1, align_steps=40,
                           top_k=4, dedup_rmsd=1.0)
     check_all(D, pk, lib, q, h, params, label="A40")
+
+
+def test_alignment_three_parts_and_lane_chunks(D, ctx):
+    # A = 70: three parts of the y range (32 + 32 + 6), 4 restarts per group
+    # (9 restarts: groups of 4, 4, 1); A = 100: four parts and one restart per
+    # group, 512 strips
+    lib = synth.library_uniform(307, 3, (12, 70), (1, 4))
+    pk = synth.pocket_gaussians(307, 4, 48, 0.5, 60, 6.0)
+    for A, R in ((70, 9), (100, 3)):
+        q = synth.start_quats(307, R)
+        print(f"[case] A={A}, R={R}", flush=True)
+        h, params = run_batch(D, ctx, pk, lib, q, torsion_steps=16, sweep_passes=1,
+                              align_steps=A, top_k=3, dedup_rmsd=1.0)
+        check_all(D, pk, lib, q, h, params, label=f"A{A}")
 
 
 def test_selection_without_lds_room(D, ctx):
