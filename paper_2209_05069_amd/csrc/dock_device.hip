@@ -537,7 +537,40 @@ __device__ __forceinline__ u64 score_free(int nfree, const uint16_t *cand, const
         csp[p] = tors[kp[p]];
         acc[p] = 0.f;
     }
-    for (int q = 0; q < m; ++q) {
+    int q = 0;
+    // U atoms at a time (up to four (atom, pass) cube loads): their loads are in
+    // flight together; the sums still take the atoms in order
+    constexpr int U = P == 1 ? 4 : (P == 2 ? 2 : 1);
+    if (Inside && U > 1) {
+        for (; q + U - 1 < m; q += U) {
+            float f[U][P][3];
+            float4 c0[U][P], c1[U][P];
+#pragma unroll
+            for (int u = 0; u < U; ++u) {
+                const float4 r0 = rec[3 * (q + u) + 0], r1 = rec[3 * (q + u) + 1],
+                             r2 = rec[3 * (q + u) + 2];
+                const int to = uniform_int(__float_as_int(r0.w));
+#pragma unroll
+                for (int p = 0; p < P; ++p) {
+                    const float gx = fmaf(csp[p].y, r2.x, fmaf(csp[p].x, r1.x, r0.x));
+                    const float gy = fmaf(csp[p].y, r2.y, fmaf(csp[p].x, r1.y, r0.y));
+                    const float gz = fmaf(csp[p].y, r2.z, fmaf(csp[p].x, r1.z, r0.z));
+                    f[u][p][0] = __builtin_amdgcn_fractf(gx);
+                    f[u][p][1] = __builtin_amdgcn_fractf(gy);
+                    f[u][p][2] = __builtin_amdgcn_fractf(gz);
+                    const uint32_t off = in_cell(tr, gx, gy, gz);
+                    c0[u][p] = ldq(tr.rs, off, to);
+                    c1[u][p] = ldq(tr.rs, off, to + 16);
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < U; ++u)
+#pragma unroll
+                for (int p = 0; p < P; ++p)
+                    acc[p] += tri_blend(c0[u][p], c1[u][p], f[u][p][0], f[u][p][1], f[u][p][2]);
+        }
+    }
+    for (; q < m; ++q) {
         const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
         const int to = uniform_int(__float_as_int(r0.w));
 #pragma unroll
@@ -1566,6 +1599,7 @@ __device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, co
 // k_final's shared memory: staged ligand, per-wave alignment records, restart
 // keys and order, selection and output scratch, then (sel_lds) the batch of
 // candidate poses and the kept poses.
+
 static __host__ __device__ size_t final_sel_offset(int nmax, int waves, int R, int K) {
     const int nw = (nmax + 63) / 64;
     const size_t b = Lds::rec(nmax, nw) + (size_t)waves * (size_t)nmax * 16 + (size_t)R * 12 +
