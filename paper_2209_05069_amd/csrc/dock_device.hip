@@ -661,9 +661,10 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
     // Cq - sqrt(Aq^2 + Bq^2); pairs that cannot come closer than the bump distance
     // are skipped, and each remaining pair is tested against every candidate of
     // the lane with two FMAs.  Distances are in grid units.
-    bool bumped[C];
+    // bumped candidates as wave masks (bit = lane) per candidate slot c
+    u64 bumped[C];
 #pragma unroll
-    for (int c = 0; c < C; ++c) bumped[c] = false;
+    for (int c = 0; c < C; ++c) bumped[c] = 0ull;
     const float lim = sa.bump2g;
     const float lim_in = lim * (1.0f + 1e-4f);  // filter margin: keeps borderline pairs
     for (int q = 0; q < m; ++q) {
@@ -688,7 +689,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
                             b0 = read_lane(bq, src);
 #pragma unroll
                 for (int c = 0; c < C; ++c)
-                    bumped[c] = bumped[c] || (fmaf(b0, cs[c].y, fmaf(a0, cs[c].x, c0)) < lim);
+                    bumped[c] |= __ballot(fmaf(b0, cs[c].y, fmaf(a0, cs[c].x, c0)) < lim);
             }
         }
     }
@@ -698,7 +699,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int k = sp.first() + lane + sp.stride() * c;
-        const bool fr = k < sa.T && !bumped[c];
+        const bool fr = k < sa.T && !((bumped[c] >> lane) & 1ull);
         const u64 bm = __ballot(fr);
         if (fr)
             cand[nfree + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
