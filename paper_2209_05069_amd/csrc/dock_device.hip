@@ -667,21 +667,26 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
     for (int c = 0; c < C; ++c) bumped[c] = 0ull;
     const float lim = sa.bump2g;
     const float lim_in = lim * (1.0f + 1e-4f);  // filter margin: keeps borderline pairs
+    // static atoms of each slot as wave masks (bit = lane)
+    u64 stm[NS];
+#pragma unroll
+    for (int s = 0; s < NS; ++s) stm[s] = __ballot(st[s]);
     for (int q = 0; q < m; ++q) {
         const float4 r0 = rec[3 * q + 0], r1 = rec[3 * q + 1], r2 = rec[3 * q + 2];
         const int i = uniform_int(__float_as_int(r1.w));
         const float vv = fmaf(r1.x, r1.x, fmaf(r1.y, r1.y, r1.z * r1.z));
 #pragma unroll
         for (int s = 0; s < NS; ++s) {
-            const u64 fw = far[i * NS + s];
-            const bool el = st[s] && ((fw >> lane) & 1ull);
+            // static atoms of slot s at least bmin bonds from moving atom i
+            const u64 elm = far[i * NS + s] & stm[s];
+            if (elm == 0ull) continue;
             const float dx = r0.x - sgx[s], dy = r0.y - sgy[s], dz = r0.z - sgz[s];
             const float cq = fmaf(dx, dx, fmaf(dy, dy, fmaf(dz, dz, vv)));
             const float aq = 2.0f * fmaf(dx, r1.x, fmaf(dy, r1.y, dz * r1.z));
             const float bq = 2.0f * fmaf(dx, r2.x, fmaf(dy, r2.y, dz * r2.z));
             const float e = cq - lim_in;
-            const bool maybe = el && (e < 0.0f || e * e < fmaf(aq, aq, bq * bq));
-            u64 bal = __ballot(maybe);
+            u64 bal = elm & (__builtin_amdgcn_ballot_w64(e < 0.0f) |
+                             __builtin_amdgcn_ballot_w64(e * e < fmaf(aq, aq, bq * bq)));
             while (bal != 0ull) {
                 const int src = __ffsll((long long)bal) - 1;
                 bal &= bal - 1ull;
