@@ -497,11 +497,11 @@ __device__ __forceinline__ void torsion_frame(const Axis &A, float x, float y, f
     wz = A.ux * dy - A.uy * dx;
 }
 
+// Turn the moving atoms (mask row mrow) by (c, sn) = (cos, sin) about axis A.
 template <int NS>
-__device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, int a, int b, float c,
-                                              float sn) {
+__device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, const Axis &A,
+                                              float c, float sn) {
     const int lane = lane_id();
-    const Axis A = bond_axis(Y, a, b);
 #pragma unroll
     for (int s = 0; s < NS; ++s) {
         const bool mv = (mrow[s] >> lane) & 1ull;
@@ -723,7 +723,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
     wave_lds_sync();  // rec is rewritten next
     if (kstar != (int)kTraceNone) {
         const float2 t = sa.tors[kstar];
-        apply_torsion(Y, mrow, a, b, t.x, t.y);
+        apply_torsion(Y, mrow, A, t.x, t.y);  // the pose is unchanged since A was taken
     }
     return kstar;
 }
@@ -1594,7 +1594,8 @@ __device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, co
             if (k < sa.T) {
                 const float2 t = sa.tors[k];
                 const int2 ab = rot[b];
-                apply_torsion(Y, mask + b * NS, uniform_int(ab.x), uniform_int(ab.y), t.x, t.y);
+                apply_torsion(Y, mask + b * NS, bond_axis(Y, uniform_int(ab.x), uniform_int(ab.y)),
+                              t.x, t.y);
             }
         }
 }
