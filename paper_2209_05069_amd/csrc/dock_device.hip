@@ -219,6 +219,11 @@ __device__ __forceinline__ float tri_in(const Tri &t, float gx, float gy, float 
     return tri_blend(q0, q1, fx, fy, fz);
 }
 
+// Radius for ball_inside from its square: the hardware square root (about one
+// ulp).  Only the choice between tri_in and tri_u depends on it, the two give the
+// same value inside [0, n-2], and kInsideMargin dwarfs the error.
+__device__ __forceinline__ float ball_radius(float r2) { return __builtin_amdgcn_sqrtf(r2); }
+
 // Whether the ball of radius rad (grid units) about (cx,cy,cz), widened by
 // kInsideMargin, stays inside [0, n-2] on every axis.
 __device__ __forceinline__ bool ball_inside(const Tri &t, float cx, float cy, float cz, float rad) {
@@ -419,7 +424,7 @@ __device__ int align_pose(Pose<NS> &Y, int n, const int (&toff)[NS], float4 *rec
             const float rx = (Y.x[s] - cx) * g.inv_h, ry = (Y.y[s] - cy) * g.inv_h,
                         rz = (Y.z[s] - cz) * g.inv_h;
             out_any = out_any ||
-                      !ball_inside(tr, ex, ey, ez, sqrtf(fmaf(rx, rx, fmaf(ry, ry, rz * rz))));
+                      !ball_inside(tr, ex, ey, ez, ball_radius(fmaf(rx, rx, fmaf(ry, ry, rz * rz))));
             rec[i] = make_float4(rx, ry, rz, __int_as_float(toff[s]));
         }
     }
@@ -644,7 +649,7 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
             // every candidate of this atom lies on the circle of radius |V| about P0
             const bool in = ball_inside(tr, (px - g.ox) * g.inv_h, (py - g.oy) * g.inv_h,
                                         (pz - g.oz) * g.inv_h,
-                                        sqrtf(fmaf(vx, vx, fmaf(vy, vy, vz * vz))) * g.inv_h);
+                                        ball_radius(fmaf(vx, vx, fmaf(vy, vy, vz * vz))) * g.inv_h);
             rec[3 * q + 2] = make_float4(wx * g.inv_h, wy * g.inv_h, wz * g.inv_h, 0.f);
             out_any = out_any || !in;
         }
