@@ -907,13 +907,14 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
 // kShellPad on both sides), the cells the band crosses as face columns: for
 // vertex x-position i of cell row (j,k) the bilinear coefficients of the face
 // with corners v(i,j,k), v(i,j+1,k), v(i,j,k+1), v(i,j+1,k+1) (the first half
-// of cube (i,j,k)); cell (i,j,k) is the two consecutive columns i and i+1.  A row table indexed by (j,k) gives each row's cell range on the low-x
-// and the high-x side of the centre.  A workgroup of k_align aligns G restarts
-// of one ligand: per atom it copies that atom's band into LDS (coalesced 16-byte
-// loads; the sampling, not the copy, bounds the kernel), and all G * A * A
-// samples of the atom read LDS.  A sample whose cell is not in the band reads its cube from
-// global memory; both give the same eight values, and the transform, blend and
-// atom-order sum are those of align_pose, so the scores are bit-identical.
+// of cube (i,j,k)); cell (i,j,k) is the two consecutive columns i and i+1.  A
+// row table indexed by (j,k) gives each row's cell range on the low-x and the
+// high-x side of the centre.  A workgroup of k_align aligns GR restarts of one
+// ligand: per atom one wave streams that atom's band into LDS while the others
+// sample the previous one, and all GR * A * A samples of the atom read LDS.  A
+// sample whose cell is not in the band reads its cube from global memory; both
+// give the same values, and the transform, blend and atom-order sum are those
+// of align_pose, so the scores are bit-identical.
 constexpr float kShellPad = 0.0625f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
