@@ -1590,20 +1590,33 @@ template <int NS>
 __device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, const int2 *rot,
                             int n, int B, int r, const uint16_t *trace, const GridArgs &g,
                             const SearchArgs &sa) {
+    const int lane = lane_id();
     start_pose(Y, xyzt, n, r, g, sa);
-    const int o = (int)trace[0];
-    apply_align(Y, n, o < sa.A * sa.A ? o : 0, sa);  // indices come from k_dock; bound anyway
-    int d = 1;
-    for (int p = 0; p < sa.P; ++p)
-        for (int b = 0; b < B; ++b, ++d) {
-            const int k = trace[d];
-            if (k < sa.T) {
-                const float2 t = sa.tors[k];
+    // The trace and each step's (cos, sin) are loaded 64 entries at a time, one
+    // entry per lane, so the replay waits for one round of loads per 64 steps
+    // instead of one per step; entry 0 is the alignment, entry 1 + p*B + b the
+    // step of bond b in pass p.
+    const int D = 1 + sa.P * B;
+    for (int base = 0; base < D; base += 64) {
+        const int e = base + lane;
+        const int kl = e < D ? (int)trace[e] : (int)kTraceNone;
+        const float2 tl = e > 0 && kl < sa.T ? sa.tors[kl] : make_float2(1.f, 0.f);
+        const int cnt = D - base < 64 ? D - base : 64;
+        for (int u = 0; u < cnt; ++u) {
+            const int d = base + u;
+            const int k = __builtin_amdgcn_readlane(kl, u);
+            if (d == 0) {
+                apply_align(Y, n, k < sa.A * sa.A ? k : 0, sa);  // from k_dock; bound anyway
+            } else if (k < sa.T) {
+                const int b = (d - 1) % B;
+                const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tl.x), u));
+                const float sn = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(tl.y), u));
                 const int2 ab = rot[b];
                 apply_torsion(Y, mask + b * NS, bond_axis(Y, uniform_int(ab.x), uniform_int(ab.y)),
-                              t.x, t.y);
+                              c, sn);
             }
         }
+    }
 }
 
 // ---------------------------------------------------------------------------
