@@ -479,7 +479,9 @@ __device__ __forceinline__ Axis bond_axis(const Pose<NS> &Y, int a, int b) {
     pick_atom(Y, a, A.ax, A.ay, A.az);
     pick_atom(Y, b, bx, by, bz);
     const float dx = bx - A.ax, dy = by - A.ay, dz = bz - A.az;
-    const float inv = 1.0f / sqrtf(dx * dx + dy * dy + dz * dz);
+    // unit axis from the hardware reciprocal square root (about one ulp, as
+    // against two roundings for a square root and a divide)
+    const float inv = __builtin_amdgcn_rsqf(dx * dx + dy * dy + dz * dz);
     A.ux = dx * inv;
     A.uy = dy * inv;
     A.uz = dz * inv;
