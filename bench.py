@@ -33,8 +33,8 @@ PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector peak (256 CU x 2.4 GHz x 256 flo
 # rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
 # plain 256 MiB copy read in the same program).  Valid only for the kernel
 # source they were taken on (sha256 prefix below); reported as null otherwise.
-TRAFFIC_SOURCE_SHA = "6bd70382af489942"
-TRAFFIC_BYTES_PER_STEP = 1.578254e+11
+TRAFFIC_SOURCE_SHA = "a83b5a6b62d2e1b2"
+TRAFFIC_BYTES_PER_STEP = 1.583570e+11
 
 
 def parse():
