@@ -60,18 +60,21 @@ def parse():
     ap.add_argument("--sweep-plain-ligands", type=int, default=2000,
                     help="ligands per size-grid cell timed in the plain form")
     ap.add_argument("--sweep-library", type=str, default="100,1000,10000,100000,1000000")
+    ap.add_argument("--torsion-steps", type=int, default=None,
+                    help="override T (e.g. 10: the paper's 36-degree torsion steps)")
     ap.add_argument("--copy-ref-mib", type=int, default=0,
                     help="run one plain device copy of this size first (reference kernel "
                          "for scaling hardware byte counters)")
     return ap.parse_args()
 
 
-def kernel_traffic(cfg, L):
+def kernel_traffic(cfg, L, s):
     import hashlib
     src = os.path.join(ROOT, "paper_2209_05069_amd", "csrc", "dock_device.hip")
     sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
     import synth
-    if sha == TRAFFIC_SOURCE_SHA and cfg == 2 and L == synth.CONFIGS[2]["ligands"]["L"]:
+    if (sha == TRAFFIC_SOURCE_SHA and cfg == 2 and L == synth.CONFIGS[2]["ligands"]["L"]
+            and s == synth.CONFIGS[2]["search"]):
         return TRAFFIC_BYTES_PER_STEP
     return None
 
@@ -314,6 +317,8 @@ def main():
 
     t0 = time.time()
     pk, lib, q, s = synth.config(a.config, n_ligands=a.ligands)
+    if a.torsion_steps is not None:
+        s = dict(s, torsion_steps=a.torsion_steps)
     print(f"[bench] workload ready in {time.time() - t0:.1f}s: {lib.n_ligands} ligands, "
           f"{int(lib.atom_off[-1])} atoms, {int(lib.rot_off[-1])} rotatable bonds",
           file=sys.stderr, flush=True)
@@ -402,7 +407,7 @@ def main():
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": kernel_traffic(a.config, L),
+            "traffic": kernel_traffic(a.config, L, s),
             "traffic_unit": "bytes per step (docking kernels, HBM side of L2)",
             "kernel": "k_align + k_dock (all size bins of one step)",
             "flop_per_step": samples * FLOP_PER_SAMPLE,
