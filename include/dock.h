@@ -2,8 +2,8 @@
  * dock.h -- C ABI of the MI355X (gfx950) geometric-docking library.
  *
  * The library docks ligands into a rigid pocket with the greedy multi-restart
- * method of Alg. 1 in Vitali et al., "Exploring the trade-off between latency
- * and batched GPU implementations of a virtual screening application"
+ * method of Alg. 1 in Vitali et al., "GPU-optimized Approaches to Molecular
+ * Docking-based Virtual Screening in Drug Discovery: A Comparative Analysis"
  * (arXiv:2209.05069), Section "Application Description":
  *   for each ligand and each restart r:
  *     Generate_Starting_Pose: the ligand, centred on its centroid, is turned by

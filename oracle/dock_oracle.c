@@ -1,7 +1,7 @@
 /*
  * dock_oracle.c -- plain single-threaded FP64 reference of the geometric docking
- * hot path (Alg. 1 of Vitali et al., "Exploring the trade-off between latency and
- * batched GPU implementations of a virtual screening application",
+ * hot path (Alg. 1 of Vitali et al., "GPU-optimized Approaches to Molecular
+ * Docking-based Virtual Screening in Drug Discovery: A Comparative Analysis",
  * arXiv:2209.05069; Section "Application Description").
  *
  * TEST INFRASTRUCTURE ONLY.  This file is the oracle the GPU library is checked
@@ -39,6 +39,8 @@
  * its own argmax or a near-tie (score within tie_rel*max(1,|best|), or a bump
  * decided by a pair distance within bump_tol of bump_dist), counts the cases,
  * and continues with the given choice so later decisions stay comparable.
+ * Each followed decision gets a class (exact, score tie, bump tie, mismatch),
+ * written per decision when the caller asks for it.
  */
 #include <math.h>
 #include <stdint.h>
@@ -259,13 +261,26 @@ typedef struct {
     const or_ligand *L;
     const or_params *P;
     const or_follow *F;
-    int32_t *topo;   /* [n][n] */
-    double *stats;   /* follow statistics */
+    int32_t *topo;     /* [n][n] */
+    double *stats;     /* follow statistics */
+    uint8_t *cls_out;  /* where the class of the next followed decision goes, or NULL */
 } ctx_t;
 
 static double tie_tol(const ctx_t *C, double best) {
     double m = fabs(best) > 1.0 ? fabs(best) : 1.0;
     return C->F->tie_rel * m;
+}
+
+/* Count a followed decision of class cls; gap = best score minus the score of
+ * the given choice (score ties only). */
+static void record(const ctx_t *C, int cls, double gap) {
+    C->stats[0] += 1;
+    C->stats[1 + cls] += 1;
+    if (cls == OR_SCORE_TIE) {
+        if (gap > C->stats[6]) C->stats[6] = gap;
+        if (gap > OR_ABS_TIE) C->stats[7] += 1;
+    }
+    if (C->cls_out) *C->cls_out = (uint8_t)cls;
 }
 
 /* Alignment of pose Y (in place).  Returns the chosen orientation index. */
@@ -285,13 +300,11 @@ static int align_pose(const ctx_t *C, double *Y, int follow_idx) {
     }
     int use = best_o;
     if (follow_idx >= 0) {
-        C->stats[0] += 1;
-        if (follow_idx >= NO) C->stats[4] += 1;
-        else if (follow_idx == best_o) C->stats[1] += 1;
-        else if (best - S[follow_idx] <= tie_tol(C, best)) {
-            C->stats[2] += 1;
-            if (best - S[follow_idx] > C->stats[6]) C->stats[6] = best - S[follow_idx];
-        } else C->stats[4] += 1;
+        if (follow_idx >= NO) record(C, OR_MISMATCH, 0.0);
+        else if (follow_idx == best_o) record(C, OR_EXACT, 0.0);
+        else if (best - S[follow_idx] <= tie_tol(C, best))
+            record(C, OR_SCORE_TIE, best - S[follow_idx]);
+        else record(C, OR_MISMATCH, 0.0);
         if (follow_idx < NO) use = follow_idx;
     }
     oracle_align_matrix(A, use, M);
@@ -386,33 +399,29 @@ static int torsion_decision(const ctx_t *C, int b, double *Y, int follow_k, doub
             if (!hit && S[k] > best) { best = S[k]; best_k = k; }
             if (D[k] >= bd + tol && S[k] > best_sure) best_sure = S[k];
         }
-        C->stats[0] += 1;
         /* diagnostic: candidates scoring above the applied one (all bumped when the
          * applied one is the best bump-free candidate) */
         if (follow_k >= 0 && follow_k < T)
             for (int k = 0; k < T; ++k)
                 if (S[k] > S[follow_k]) C->stats[5] += 1;
         if (follow_k == (int)NONE_ACCEPTED) {
-            if (best_k < 0) C->stats[1] += 1;
-            else if (best_sure == -INFINITY) C->stats[3] += 1;  /* only near-boundary candidates */
-            else C->stats[4] += 1;
+            if (best_k < 0) record(C, OR_EXACT, 0.0);
+            else if (best_sure == -INFINITY) record(C, OR_BUMP_TIE, 0.0); /* only near-boundary candidates */
+            else record(C, OR_MISMATCH, 0.0);
         } else if (follow_k >= T) {
-            C->stats[4] += 1;
+            record(C, OR_MISMATCH, 0.0);
         } else if (follow_k == best_k) {
-            C->stats[1] += 1;
+            record(C, OR_EXACT, 0.0);
         } else {
             int given_ok = D[follow_k] >= bd - tol;                 /* not surely bumped */
             double ref = best_sure;                                 /* best surely-free score */
             if (given_ok && (ref == -INFINITY || S[follow_k] >= ref - tie_tol(C, ref))) {
                 if (D[follow_k] < bd || (best_k >= 0 && best - S[follow_k] > tie_tol(C, best)))
-                    C->stats[3] += 1;                               /* decided by a bump near-tie */
-                else {
-                    C->stats[2] += 1;
-                    double gap = fabs(best - S[follow_k]);
-                    if (gap > C->stats[6]) C->stats[6] = gap;
-                }
+                    record(C, OR_BUMP_TIE, 0.0);                    /* decided by a bump near-tie */
+                else
+                    record(C, OR_SCORE_TIE, fabs(best - S[follow_k]));
             } else {
-                C->stats[4] += 1;
+                record(C, OR_MISMATCH, 0.0);
             }
         }
         chosen = follow_k;
@@ -439,7 +448,10 @@ int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
     ctx_t C;
     C.g = g; C.L = L; C.P = P; C.F = F;
     C.stats = out->stats;
+    C.cls_out = NULL;
     for (int s = 0; s < 8; ++s) out->stats[s] = 0.0;
+    if (out->decision_class) memset(out->decision_class, OR_NOT_FOLLOWED, (size_t)R * D);
+    if (out->final_class) memset(out->final_class, OR_NOT_FOLLOWED, (size_t)P->top_k);
     C.topo = (int32_t *)malloc(sizeof(int32_t) * n * n);
     oracle_topo(n, L->nbonds, L->bonds, C.topo);
 
@@ -470,6 +482,7 @@ int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
             out->decision_score[(size_t)r * DS] = oracle_score(g, n, L->type, Y);
         /* Alignment */
         const uint16_t *ftr = F ? F->trace + (size_t)r * D : NULL;
+        C.cls_out = out->decision_class ? out->decision_class + (size_t)r * D : NULL;
         int o = align_pose(&C, Y, ftr ? (int)ftr[0] : -1);
         if (out->trace) out->trace[(size_t)r * D] = (uint16_t)o;
         if (out->decision_score)
@@ -479,6 +492,7 @@ int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
         for (int p = 0; p < P->sweep_passes; ++p)
             for (int b = 0; b < L->nrot; ++b, ++d) {
                 double sa;
+                C.cls_out = out->decision_class ? out->decision_class + (size_t)r * D + d : NULL;
                 int k = torsion_decision(&C, b, Y, ftr ? (int)ftr[d] : -1, &sa);
                 if (out->trace) out->trace[(size_t)r * D + d] = (uint16_t)k;
                 if (out->decision_score) out->decision_score[(size_t)r * DS + 1 + d] = sa;
@@ -506,11 +520,12 @@ int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
     int *fidx = (int *)malloc(sizeof(int) * (ns > 0 ? ns : 1));
     for (int s = 0; s < ns; ++s) {
         int r = sel[s];
-        if (r < 0 || r >= R) { r = 0; C.stats[4] += 1; }
+        if (r < 0 || r >= R) { r = 0; C.stats[4] += 1; }  /* not a decision: kept restart out of range */
         memcpy(Y, poses + (size_t)r * 3 * n, sizeof(double) * 3 * n);
         fidx[s] = 0;
         if (P->final_align) {
             int fo = (F && F->final_trace) ? (int)F->final_trace[s] : -1;
+            C.cls_out = (out->final_class && s < P->top_k) ? out->final_class + s : NULL;
             fidx[s] = align_pose(&C, Y, fo);
         }
         memcpy(fpose + (size_t)s * 3 * n, Y, sizeof(double) * 3 * n);

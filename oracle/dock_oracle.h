@@ -41,6 +41,11 @@ typedef struct {
     double tie_rel, bump_tol;
 } or_follow;
 
+/* Class of a followed decision (decision_class / final_class entries). */
+enum { OR_EXACT = 0, OR_SCORE_TIE = 1, OR_BUMP_TIE = 2, OR_MISMATCH = 3, OR_NOT_FOLLOWED = 255 };
+/* Score ties whose gap exceeds this absolute amount are counted in stats[7]. */
+#define OR_ABS_TIE 1e-5
+
 typedef struct {
     double *restart_score;   /* [R] or NULL */
     double *restart_pose;    /* [R][n][3] or NULL */
@@ -51,8 +56,11 @@ typedef struct {
     double *pose_score;      /* [top_k] or NULL */
     double *pose_xyz;        /* [top_k][n][3] or NULL */
     uint16_t *final_trace;   /* [top_k] or NULL */
+    uint8_t *decision_class; /* [R][1 + passes*nrot] class of each followed decision, or NULL */
+    uint8_t *final_class;    /* [top_k] class of each followed final alignment, or NULL */
     /* follow statistics: decisions, exact, score ties, bump ties, mismatches,
-     * candidates scoring above the applied torsion step (summed), max tie gap, - */
+     * candidates scoring above the applied torsion step (summed), max tie gap,
+     * score ties whose gap exceeds OR_ABS_TIE */
     double stats[8];
 } or_result;
 

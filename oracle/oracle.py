@@ -15,6 +15,9 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "dock_oracle.c")
 _LIBPATH = os.path.join(_HERE, "liboracle.so")
 NONE_ACCEPTED = 0xFFFF
+# class of a followed decision (decision_class / final_class)
+EXACT, SCORE_TIE, BUMP_TIE, MISMATCH, NOT_FOLLOWED = 0, 1, 2, 3, 255
+ABS_TIE = 1e-5
 
 
 def build(force: bool = True) -> str:
@@ -57,7 +60,8 @@ class _Follow(ctypes.Structure):
 class _Result(ctypes.Structure):
     _fields_ = [("restart_score", P), ("restart_pose", P), ("decision_score", P), ("trace", P),
                 ("n_sel", ctypes.c_int32), ("sel_restart", P), ("pose_score", P),
-                ("pose_xyz", P), ("final_trace", P), ("stats", ctypes.c_double * 8)]
+                ("pose_xyz", P), ("final_trace", P), ("decision_class", P),
+                ("final_class", P), ("stats", ctypes.c_double * 8)]
 
 
 _lib = None
@@ -212,10 +216,13 @@ def dock_ligand(grid, lig, quats, follow=None, decisions=False, **params):
         pose_score=np.zeros(max(K, 1), np.float64),
         pose_xyz=np.zeros((max(K, 1), n, 3), np.float64),
         final_trace=np.zeros(max(K, 1), np.uint16),
+        decision_class=np.zeros((R, D), np.uint8),
+        final_class=np.zeros(max(K, 1), np.uint8),
     )
     res = _Result(_ptr(out["restart_score"]), _ptr(out["restart_pose"]),
                   _ptr(out["decision_score"]), _ptr(out["trace"]), 0, _ptr(out["sel_restart"]),
-                  _ptr(out["pose_score"]), _ptr(out["pose_xyz"]), _ptr(out["final_trace"]))
+                  _ptr(out["pose_score"]), _ptr(out["pose_xyz"]), _ptr(out["final_trace"]),
+                  _ptr(out["decision_class"]), _ptr(out["final_class"]))
     fs = None
     keep = []
     if follow is not None:
@@ -234,11 +241,13 @@ def dock_ligand(grid, lig, quats, follow=None, decisions=False, **params):
         raise ValueError(f"oracle_dock_ligand rejected the input ({rc})")
     ns = res.n_sel
     out["n_sel"] = ns
-    for k in ("sel_restart", "pose_score", "pose_xyz", "final_trace"):
+    for k in ("sel_restart", "pose_score", "pose_xyz", "final_trace", "final_class"):
         out[k] = out[k][:ns].copy()
     st = list(res.stats)
+    # score_ties: gap within tie_rel*max(1,|best|); score_ties_beyond_abs: of those, the
+    # ties whose gap exceeds ABS_TIE (they would be mismatches under an absolute tolerance)
     out["stats"] = dict(decisions=int(st[0]), exact=int(st[1]), score_ties=int(st[2]),
                         bump_ties=int(st[3]), mismatches=int(st[4]), above_applied=int(st[5]),
-                        max_tie_gap=st[6])
+                        max_tie_gap=st[6], score_ties_beyond_abs=int(st[7]))
     out["best_score"] = float(out["pose_score"][0]) if ns else float("-inf")
     return out

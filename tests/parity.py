@@ -72,9 +72,11 @@ def check_ligand(grid, lig, quats, params, g, stats=None):
         g["n_poses"] if params.final_align else 0)
     # restart scores
     S = o["restart_score"]
+    rerr = 0.0
     if "restart_score" in g:
         err = np.abs(g["restart_score"] - S) / np.maximum(1.0, np.abs(S))
         assert err.max() <= SCORE_REL, f"restart score rel err {err.max()}"
+        rerr = float(err.max())
     check_selection(g["pose_restart"], S, o["restart_pose"], params.top_k, params.dedup_rmsd)
     # final poses and scores (oracle keeps the GPU's output order in follow mode)
     fs = o["pose_score"]
@@ -88,8 +90,11 @@ def check_ligand(grid, lig, quats, params, g, stats=None):
     if g["n_poses"]:
         assert g["best_score"] == g["pose_score"][0]
     if stats is not None:
-        for k in ("decisions", "exact", "score_ties", "bump_ties"):
+        for k in ("decisions", "exact", "score_ties", "score_ties_beyond_abs", "bump_ties"):
             stats[k] = stats.get(k, 0) + st[k]
+        stats["ligands"] = stats.get("ligands", 0) + 1
+        stats["max_restart_rel_err"] = max(stats.get("max_restart_rel_err", 0.0), rerr)
+        stats["max_tie_gap"] = max(stats.get("max_tie_gap", 0.0), float(st["max_tie_gap"]))
         stats["max_final_rel_err"] = max(stats.get("max_final_rel_err", 0.0), float(err.max(initial=0)))
         stats["max_pose_rmsd"] = max(stats.get("max_pose_rmsd", 0.0),
                                      max((rmsd(g["pose_xyz"][s], o["pose_xyz"][s])
