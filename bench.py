@@ -1,16 +1,19 @@
 """Throughput benchmark of the docking hot path on one MI355X.
 
-Workload (default): the paper-scale synthetic library -- 10,000 random-tree
-ligands with U{20..80} heavy atoms and U{2..12} rotatable bonds, a 4-type
-96^3 pocket at 0.375 A (160 Gaussians per type), 256 restarts, 256 torsion
-steps, 3 sweep passes, 30x30 alignment, top-30 poses with 2 A dedup.
-A step docks the whole library (every stage of the hot path) with inputs
-already resident in device memory.
+Workload (default): the large batched library -- 200,000 random-tree ligands
+with U{20..100} heavy atoms and U{0..20} rotatable bonds (clipped to what the
+tree allows), a 4-type 96^3 pocket at 0.375 A (160 Gaussians per type), 256
+restarts, 256 torsion steps, 3 sweep passes, 30x30 alignment, top-30 poses
+with 2 A dedup.  A step docks the whole library (every stage of the hot path)
+with inputs already resident in device memory.
 
 Prints one JSON line.  `value` is ligands docked per second.  The roofline
-object covers the dominant kernel (the per-restart docking kernels), timed live
-with HIP events on the stream they run on; `cpu_baseline` times the FP64
-oracle, single-threaded, on a bounded sample of the same library.
+object covers the dominant kernel (the alignment or the torsion-sweep kernels
+of a step, whichever takes longer), timed live with HIP events on the stream
+they run on; `cpu_baseline` times the FP64 oracle, single-threaded, on a
+bounded sample of the same library stratified by size.  The plain per-ligand
+form is timed on a stratified sample of the same library for the
+batched/plain factor, and one ligand at a time for its per-ligand latency.
 """
 import argparse
 import json
@@ -27,27 +30,34 @@ sys.path.insert(0, ROOT)
 # rigid transform 18 (3x3 matrix-vector + translation), grid coordinates 6,
 # cell fractions 3, trilinear blend 21 (7 lerps x 3), accumulate 1.
 FLOP_PER_SAMPLE = 49
-PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector peak (256 CU x 2.4 GHz x 256 flop/clk)
+PEAK_FP32_TFLOPS = 157.3   # MI355X fp32 vector peak (256 CU x 2.4 GHz x 256 flop/clk, packed)
+PEAK_FP32_NONPACKED_TFLOPS = 78.6  # one wave64 FMA per CU per clock (packed FP32 not used)
 
-# HBM bytes of the docking kernels (k_align + k_dock) per step of the default workload, from two
-# rocprofv3 --pmc runs (FETCH_SIZE x 2.000, WRITE_SIZE x 1.000, the factors a
-# plain 256 MiB copy read in the same program).  Valid only for the kernel
-# source they were taken on (sha256 prefix below); reported as null otherwise.
-TRAFFIC_SOURCE_SHA = "a83b5a6b62d2e1b2"
-TRAFFIC_BYTES_PER_STEP = 1.583570e+11
+# HBM bytes of the dominant kernel per step, from two rocprofv3 --pmc runs
+# (FETCH_SIZE and WRITE_SIZE, scaled by the factors a plain 256 MiB device copy
+# read in the same program).  Valid only for the kernel source they were taken
+# on (sha256 prefix) and the workload they were taken on: reported as null
+# otherwise.  Key: (config, torsion steps, ligands) -> (kernel, source sha, bytes).
+TRAFFIC = {}
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--steps", type=int, default=6)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--config", type=int, default=2)
+    ap.add_argument("--config", type=int, default=3)
     ap.add_argument("--ligands", type=int, default=None, help="truncate the library")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="time budget of the oracle CPU baseline (0: skip)")
-    ap.add_argument("--plain-steps", type=int, default=1,
-                    help="timed steps of the plain per-ligand form on the same library (0: skip)")
+    ap.add_argument("--plain-ligands", type=int, default=512,
+                    help="ligands of the stratified sample timed in the plain per-ligand form "
+                         "(0: skip)")
+    ap.add_argument("--latency-ligands", type=int, default=32,
+                    help="ligands docked one per call in the plain form for its per-ligand "
+                         "latency (0: skip)")
+    ap.add_argument("--no-prune", action="store_true",
+                    help="the no-early-exit ablation: no bump-check pruning (bump_prune=0)")
     ap.add_argument("--serve", action="store_true",
                     help="run the serving workload (8 pockets, Poisson requests) instead")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
@@ -68,15 +78,38 @@ def parse():
     return ap.parse_args()
 
 
-def kernel_traffic(cfg, L, s):
+def source_sha():
     import hashlib
     src = os.path.join(ROOT, "paper_2209_05069_amd", "csrc", "dock_device.hip")
-    sha = hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+    return hashlib.sha256(open(src, "rb").read()).hexdigest()[:16]
+
+
+def kernel_traffic(cfg, L, s, kernel):
+    """Measured HBM bytes per step of `kernel`, or None unless they were taken on
+    this kernel source, this workload recipe, its full library and its search."""
     import synth
-    if (sha == TRAFFIC_SOURCE_SHA and cfg == 2 and L == synth.CONFIGS[2]["ligands"]["L"]
-            and s == synth.CONFIGS[2]["search"]):
-        return TRAFFIC_BYTES_PER_STEP
-    return None
+    t = TRAFFIC.get((cfg, s["torsion_steps"], L))
+    if (t is None or t[0] != kernel or t[1] != source_sha()
+            or s != synth.CONFIGS[cfg]["search"] or L != synth.CONFIGS[cfg]["ligands"]["L"]):
+        return None
+    return t[2]
+
+
+def stratified_order(lib, seed):
+    """All ligand indices, ordered so that every prefix takes the (heavy-atom
+    quartile, rotatable-bond half) cells in turn, each cell in a seeded random
+    order: a prefix is a size-stratified sample of the library."""
+    n, B = lib.n_atoms(), lib.n_rot()
+    rng = np.random.default_rng(seed)
+    qa = np.quantile(n, [0.25, 0.5, 0.75])
+    cell = np.searchsorted(qa, n, side="right") * 2 + (B > np.median(B))
+    lists = [list(rng.permutation(np.flatnonzero(cell == c))) for c in range(8)]
+    out = []
+    while any(lists):
+        for li in lists:
+            if li:
+                out.append(int(li.pop()))
+    return out
 
 
 def describe(cfg, L, s):
@@ -102,8 +135,9 @@ def workload_counts(lib, s):
     B = lib.n_rot().astype(np.int64)
     R, T, Pp, A = s["restarts"], s["torsion_steps"], s["sweep_passes"], s["align_steps"]
     # moving atoms per rotatable bond
-    m = np.array([bin(int(w)).count("1") for w in lib.rot_mask.reshape(-1)], np.int64)
-    m = m.reshape(len(lib.rot_bond), -1).sum(1) if len(lib.rot_bond) else np.zeros(0, np.int64)
+    m = (np.unpackbits(np.ascontiguousarray(lib.rot_mask).view(np.uint8), axis=None)
+         .reshape(len(lib.rot_bond), -1).sum(1).astype(np.int64)
+         if len(lib.rot_bond) else np.zeros(0, np.int64))
     lig_of_rot = np.repeat(np.arange(len(n)), B)
     moving_per_lig = np.bincount(lig_of_rot, weights=m, minlength=len(n)).astype(np.int64)
     rigid_samples = int(R * (A * A * n.sum() + n.sum()))
@@ -124,14 +158,14 @@ def _cpu_model():
 
 def cpu_baseline(pk, lib, q, s, budget_s):
     """The FP64 oracle as it stands, on ligands of the same library taken in a
-    seeded random order until the budget is spent: single-threaded (the reported
-    value), then one ligand per thread over the host cores given to this job (at
-    most 16; the oracle's C calls release the GIL)."""
+    size-stratified seeded order (stratified_order) until the budget is spent:
+    single-threaded (the reported value), then one ligand per thread over the
+    host cores given to this job (at most 16; the oracle's C calls release the
+    GIL)."""
     from concurrent.futures import ThreadPoolExecutor
     from oracle import oracle as O
     grid = O.Grid.of(pk)
-    rng = np.random.default_rng(2209)
-    order = [int(l) for l in rng.permutation(lib.n_ligands)]
+    order = stratified_order(lib, 2209)
     kw = {k: v for k, v in s.items() if k != "restarts"}
 
     def one(l):
@@ -146,8 +180,9 @@ def cpu_baseline(pk, lib, q, s, budget_s):
             break
     el = time.perf_counter() - t0
     out = dict(value=done / el, unit="ligands/s", cores=1, kind="oracle",
-               sample=f"{done} ligands of the same library (seeded random order), "
-                      f"FP64 single thread, {el:.1f} s",
+               sample=f"{done} ligands of the same library (stratified by heavy-atom quartile "
+                      f"and rotatable-bond half, seeded), full search, FP64 single thread, "
+                      f"{el:.1f} s",
                cpu_model=_cpu_model())
     nthr = max(1, min(16, len(os.sched_getaffinity(0)) if hasattr(os, "sched_getaffinity")
                       else (os.cpu_count() or 1)))
@@ -262,6 +297,8 @@ def sweep_main(a):
     q = synth.start_quats(seed, 128)
     ctx = D.dock_create(0)
     pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    if a.no_prune:
+        s["bump_prune"] = 0
     pb = D.SearchParams(q, **s)
     pp = D.SearchParams(q, mode=D.DOCK_MODE_PLAIN, **s)
     cells = []
@@ -300,6 +337,54 @@ def sweep_main(a):
                       "cells": cells, "library": lib_runs}), flush=True)
 
 
+def _events(torch, stream):
+    e = torch.cuda.Event(enable_timing=True)
+    e.record(stream)
+    return e
+
+
+def plain_form(D, torch, ctx, pid, lib, q, s, order, n_sample, n_latency, stream):
+    """The plain per-ligand form on a size-stratified sample of the library (the
+    first n_sample of `order`): ligands/s over one call, and per-ligand latency
+    from n_latency of them docked one per call (each alone on the GPU)."""
+    pparams = D.SearchParams(q, mode=D.DOCK_MODE_PLAIN, **s)
+    sub = lib.subset(order[:n_sample])
+    dsl = D.DeviceLibrary(sub)
+    rsl = D.DeviceResults(sub.n_ligands, dsl.n_atoms_total, dsl.n_rot_total, pparams)
+    warm = lib.subset(order[:8])
+    dw = D.DeviceLibrary(warm)
+    rw = D.DeviceResults(warm.n_ligands, dw.n_atoms_total, dw.n_rot_total, pparams)
+    D.dock_ligands_batch(ctx, pid, dw, pparams, rw, stream)
+    torch.cuda.synchronize()
+    p0 = _events(torch, stream)
+    D.dock_ligands_batch(ctx, pid, dsl, pparams, rsl, stream)
+    p1 = _events(torch, stream)
+    torch.cuda.synchronize()
+    pms = p0.elapsed_time(p1)
+    out = {"ligands_per_s": sub.n_ligands / (pms * 1e-3), "sample_ligands": sub.n_ligands,
+           "sample": "size-stratified (heavy-atom quartile x rotatable-bond half), seeded",
+           "ms": pms,
+           "form": "one ligand per launch sequence (checks, R restart workgroups, select/final), "
+                   "ligands round-robin over 4 streams"}
+    if n_latency > 0:
+        lat = []
+        for l in order[:n_latency]:
+            one = lib.subset([l])
+            d1 = D.DeviceLibrary(one)
+            r1 = D.DeviceResults(1, d1.n_atoms_total, d1.n_rot_total, pparams)
+            torch.cuda.synchronize()
+            a = _events(torch, stream)
+            D.dock_ligands_batch(ctx, pid, d1, pparams, r1, stream)
+            b = _events(torch, stream)
+            torch.cuda.synchronize()
+            lat.append(a.elapsed_time(b))
+        out["latency_ms"] = {"p50": float(np.percentile(lat, 50)), "p99": float(np.percentile(lat, 99)),
+                             "ligands": len(lat),
+                             "note": "one ligand per call, alone on the GPU, from its first "
+                                     "kernel to its results"}
+    return out
+
+
 def main():
     a = parse()
     if a.gpus != 1:
@@ -324,7 +409,8 @@ def main():
           file=sys.stderr, flush=True)
     ctx = D.dock_create(0)
     pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
-    params = D.SearchParams(q, **s)
+    prune = 0 if a.no_prune else 1
+    params = D.SearchParams(q, bump_prune=prune, **s)
     dl = D.DeviceLibrary(lib)
     res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params)
     stream = torch.cuda.current_stream()
@@ -344,18 +430,13 @@ def main():
     D.dock_set_timing(ctx, True)
     D.dock_get_timing(ctx)
     torch.cuda.synchronize()
-    e0 = torch.cuda.Event(enable_timing=True)
-    e1 = torch.cuda.Event(enable_timing=True)
     step_ms = []
-    e0.record(stream)
+    e0 = _events(torch, stream)
     for k in range(a.steps):
-        es = torch.cuda.Event(enable_timing=True)
-        ee = torch.cuda.Event(enable_timing=True)
-        es.record(stream)
+        es = _events(torch, stream)
         D.dock_ligands_batch(ctx, pid, dl, params, res, stream)
-        ee.record(stream)
-        step_ms.append((es, ee))
-    e1.record(stream)
+        step_ms.append((es, _events(torch, stream)))
+    e1 = _events(torch, stream)
     torch.cuda.synchronize()
     total_ms = e0.elapsed_time(e1)
     per_step = [x.elapsed_time(y) for x, y in step_ms]
@@ -368,13 +449,29 @@ def main():
     ms = total_ms / a.steps
     rigid_samples, torsion_all, tors = workload_counts(lib, s)
     calls = max(1, tm["calls"])
-    dock_ms = tm["dock_ms"] / calls
-    # Algorithmic work: as in Alg. 1 a torsion candidate that fails the bump check
-    # is not scored, so only the scored torsion samples (counted by the kernels)
-    # enter, next to the rigid samples.
-    torsion_scored = tm["scored_samples"] // calls
-    samples = rigid_samples + torsion_scored
-    achieved = samples * FLOP_PER_SAMPLE / (dock_ms * 1e-3) / 1e12
+    align_ms = tm["align_ms"] / calls
+    torsion_ms = (tm["dock_ms"] - tm["align_ms"]) / calls
+    # Algorithmic work per step.  Alignment (k_align): R * A^2 * n atom samples per
+    # ligand.  Torsion sweep (k_dock): as in Alg. 1 a candidate that fails the bump
+    # check is not scored, so only the scored torsion samples (counted by the
+    # kernels) enter, plus the pose score of every restart (R * n).
+    n_tot = int(lib.atom_off[-1])
+    align_samples = s["restarts"] * s["align_steps"] ** 2 * n_tot
+    scored = tm["scored_samples"] // calls
+    if a.no_prune:
+        scored = torsion_all  # every candidate is scored, as Alg. 1 scores the bump-free ones
+    torsion_samples = scored + s["restarts"] * n_tot
+    kernels = {
+        "k_align": dict(ms_per_step=align_ms, atom_samples_per_step=align_samples,
+                        achieved_tflops=align_samples * FLOP_PER_SAMPLE / (align_ms * 1e-3) / 1e12),
+        "k_dock": dict(ms_per_step=torsion_ms, atom_samples_per_step=torsion_samples,
+                       torsion_samples_scored=scored,
+                       torsion_samples_all_candidates=torsion_all,
+                       achieved_tflops=torsion_samples * FLOP_PER_SAMPLE / (torsion_ms * 1e-3) / 1e12),
+    }
+    dom = max(kernels, key=lambda k: kernels[k]["ms_per_step"])
+    kd = kernels[dom]
+    achieved = kd["achieved_tflops"]
     rigid = int(s["restarts"] * L * s["align_steps"] ** 2 +
                 int(res.n_poses.sum().item()) * s["align_steps"] ** 2)
     out = {
@@ -391,7 +488,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {
-            "workload": describe(a.config, L, s),
+            "workload": describe(a.config, L, s) + ("; no bump-check pruning (ablation)"
+                                                    if a.no_prune else ""),
             "form": "batched (persistent wavefront-per-restart kernels, size-binned)",
             "ligands": L,
         },
@@ -399,51 +497,32 @@ def main():
         "rigid_evals_per_s": rigid / (ms * 1e-3),
         "latency_ms": {"p50": float(np.percentile(per_step, 50)),
                        "p99": float(np.percentile(per_step, 99)),
-                       "note": "batched form: every ligand of a step completes with the step"},
-        "phases_ms": {k: tm[k] / max(1, tm["calls"]) for k in ("prep_ms", "dock_ms", "final_ms")},
+                       "note": "batched form: every ligand of a step is submitted at its start "
+                               "and completes with it, so a ligand's latency is the step's"},
+        "phases_ms": {k: tm[k] / calls for k in ("prep_ms", "align_ms", "dock_ms", "final_ms")},
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
             "peak": PEAK_FP32_TFLOPS,
             "unit": "TFLOP/s",
             "frac": achieved / PEAK_FP32_TFLOPS,
-            "traffic": kernel_traffic(a.config, L, s),
-            "traffic_unit": "bytes per step (docking kernels, HBM side of L2)",
-            "kernel": "k_align + k_dock (all size bins of one step)",
-            "flop_per_step": samples * FLOP_PER_SAMPLE,
-            "atom_samples_per_step": samples,
-            "rigid_samples_per_step": rigid_samples,
-            "torsion_samples_scored_per_step": torsion_scored,
-            "torsion_samples_all_candidates_per_step": torsion_all,
-            "dock_ms_per_step": dock_ms,
+            "traffic": kernel_traffic(a.config, L, s, dom),
+            "traffic_unit": "bytes per step (dominant kernel, HBM side of L2)",
+            "kernel": f"{dom} (all size bins of one step)",
+            "flop_per_step": kd["atom_samples_per_step"] * FLOP_PER_SAMPLE,
+            "peak_non_packed": PEAK_FP32_NONPACKED_TFLOPS,
+            "frac_non_packed": achieved / PEAK_FP32_NONPACKED_TFLOPS,
+            "kernels": kernels,
         },
     }
-    if a.plain_steps > 0:
-        pparams = D.SearchParams(q, mode=D.DOCK_MODE_PLAIN, **s)
-        small = lib.subset(range(min(64, L)))
-        dsl = D.DeviceLibrary(small)
-        rsl = D.DeviceResults(small.n_ligands, dsl.n_atoms_total, dsl.n_rot_total, pparams)
-        D.dock_ligands_batch(ctx, pid, dsl, pparams, rsl, stream)
-        torch.cuda.synchronize()
-        pres = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, pparams)
-        p0 = torch.cuda.Event(enable_timing=True)
-        p1 = torch.cuda.Event(enable_timing=True)
-        p0.record(stream)
-        for k in range(a.plain_steps):
-            D.dock_ligands_batch(ctx, pid, dl, pparams, pres, stream)
-        p1.record(stream)
-        torch.cuda.synchronize()
-        pms = p0.elapsed_time(p1) / a.plain_steps
-        same = bool(torch.equal(pres.best_score, res.best_score))
-        out["plain_form"] = {
-            "ligands_per_s": L / (pms * 1e-3), "ms_per_step": pms, "steps": a.plain_steps,
-            "torsion_evals_per_s": tors / (pms * 1e-3),
-            "batched_over_plain": pms / ms,
-            "same_best_scores_as_batched": same,
-            "form": "one ligand per launch sequence (checks, R restart workgroups of 4 waves, "
-                    "select/final), ligands round-robin over 4 streams",
-        }
-        print(f"[bench] plain form {pms:.1f} ms/step", file=sys.stderr, flush=True)
+    order = stratified_order(lib, 2209)
+    if a.plain_ligands > 0:
+        pf = plain_form(D, torch, ctx, pid, lib, q, dict(s, bump_prune=prune), order,
+                        min(a.plain_ligands, L), min(a.latency_ligands, L), stream)
+        pf["batched_over_plain"] = out["value"] / pf["ligands_per_s"]
+        out["plain_form"] = pf
+        print(f"[bench] plain form {pf['ligands_per_s']:.0f} ligands/s", file=sys.stderr,
+              flush=True)
     D.dock_destroy(ctx)
     if a.cpu_seconds > 0:
         print("[bench] cpu baseline (oracle) ...", file=sys.stderr, flush=True)

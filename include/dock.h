@@ -74,8 +74,14 @@ typedef enum {
 #define DOCK_MAX_TOP_K 64
 #define DOCK_TRACE_NONE 0xFFFFu /* torsion decision where every candidate bumped */
 
-/* Create a context on HIP device `device` (its index as hipSetDevice takes it). */
-int dock_create(int device, dock_ctx **out);
+/* Create a context on HIP device `device` (its index as hipSetDevice takes it).
+ * hbm_budget_bytes bounds the device memory the context's dock_submit work may
+ * hold at once (library copies, results and workspaces of requests not yet
+ * retired by dock_poll/dock_wait, plus the per-stream workspaces kept between
+ * requests); 0 = no fixed budget, admit against the device's free memory less
+ * a 1 GiB reserve.  (The paper's batched form sizes its batches from the memory
+ * and occupancy of the GPU; Batched Implementation subsection.) */
+int dock_create(int device, uint64_t hbm_budget_bytes, dock_ctx **out);
 /* Wait for all submitted work, free every device buffer of the context. */
 int dock_destroy(dock_ctx *ctx);
 /* Message of the calling thread's last failure ("" if none).  Valid until the
@@ -142,6 +148,14 @@ typedef struct {
     int32_t final_align;       /* 0 or 1 */
     int32_t bump_min_bonds;    /* >= 1; pairs closer in bonds are never checked */
     int32_t mode;              /* DOCK_MODE_* */
+    int32_t bump_prune;        /* 1: prune the Bump Check (pairs that cannot come within
+                                  bump_dist for any angle are skipped, and only
+                                  candidates that pass it are scored); 0: no pruning,
+                                  every eligible pair is tested against every candidate
+                                  and every candidate is scored, the bump verdict applied
+                                  afterwards.  The selected steps are the same either
+                                  way; 0 is the no-early-exit ablation of the paper's
+                                  workload analysis (Execution Profiling). */
     float bump_dist;           /* Angstrom, >= 0 */
     float dedup_rmsd;          /* Angstrom, >= 0 (0: plain top-K) */
     const float *start_quat;   /* HOST [restarts][4] */
@@ -187,10 +201,19 @@ int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
 /* Asynchronous form on host memory (paper: the batched form's asynchronous
  * interface, Batched Implementation subsection).  The library and params are
  * copied before the call returns; `out` must stay valid until dock_poll reports
- * done (or dock_wait returns).  Admission: DOCK_EAGAIN when the request does not
- * fit in the device memory left free (less a reserve); retry after polling. */
+ * done (or dock_wait returns).  Admission: DOCK_EAGAIN when the request's device
+ * memory does not fit in the context's budget (see dock_create) next to the work
+ * already admitted, or, without a budget, in the device memory left free (less
+ * a reserve); nothing is enqueued then: retry after polling. */
 int dock_submit(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
                 const dock_params *params, dock_results *out, uint64_t *ticket);
+/* Device bytes a dock_submit of this request needs on a stream that holds no
+ * workspace yet: the copies of the library and the results, held until the
+ * ticket retires, plus the docking workspace; the figure the admission check
+ * compares with the budget.  Reads only the sizes in lib, params and which
+ * optional outputs of out are requested (no device work, no context). */
+int dock_request_bytes(const dock_library *lib, const dock_params *params,
+                       const dock_results *out, uint64_t *bytes);
 /* *done = 1 once the results of `ticket` are in `out` (the ticket is then
  * retired; polling it again gives DOCK_ENOENT). */
 int dock_poll(dock_ctx *ctx, uint64_t ticket, int32_t *done);
@@ -199,7 +222,8 @@ int dock_wait(dock_ctx *ctx, uint64_t ticket);
 
 /* Phase timing, for measurement.  While enabled, every dock_ligands_batch
  * call records HIP events on its own stream before its prep kernel, after it,
- * after the docking kernels and after the select/final kernels.
+ * after the alignment kernels (batched form), after the docking kernels and
+ * after the select/final kernels.
  * dock_get_timing waits for every recorded event, returns the summed
  * milliseconds of each phase, the number of calls and the number of torsion
  * samples the docking kernels scored since the last dock_get_timing, and starts
@@ -209,6 +233,8 @@ int dock_wait(dock_ctx *ctx, uint64_t ticket);
 typedef struct {
     double prep_ms;   /* ligand checks, bump-pair rows, size binning */
     double dock_ms;   /* restarts: start pose, alignment, torsion sweeps */
+    double align_ms;  /* the alignment kernels' part of dock_ms (batched form; 0 in the
+                         plain form, whose restart kernel also aligns) */
     double final_ms;  /* pose selection, final rigid step, outputs */
     int64_t calls;
     int64_t scored_samples;  /* torsion samples scored in the docking phase */

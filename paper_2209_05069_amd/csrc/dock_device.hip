@@ -219,6 +219,9 @@ __device__ __forceinline__ float tri_in(const Tri &t, float gx, float gy, float 
     return tri_blend(q0, q1, fx, fy, fz);
 }
 
+// Flag of a listed torsion candidate that bumps (see score_free).
+constexpr int kCandBumped = 0x8000;
+
 // Radius for ball_inside from its square: the hardware square root (about one
 // ulp).  Only the choice between tri_in and tri_u depends on it, the two give the
 // same value inside [0, n-2], and kInsideMargin dwarfs the error.
@@ -525,22 +528,27 @@ __device__ __forceinline__ void apply_torsion(Pose<NS> &Y, const u64 *mrow, cons
 // One torsion decision (Optimize Pose, inner angle loop) for rotatable bond with
 // moving-mask row mrow (NS words), axis atoms (a,b).  cs[c] = (cos,sin) of this
 // lane's candidates k = lane + 64c.  Returns the applied step or kTraceNone.
-// Best key (score, candidate) among the nfree bump-free candidates of a torsion
-// step listed in cand, scored on the moving fragment (frames of m moving atoms in
+// Best key (score, candidate) among the nfree candidates of a torsion step
+// listed in cand, scored on the moving fragment (frames of m moving atoms in
 // rec): lanes take the listed candidates in P passes of 64, each candidate's sum
-// runs over the atoms in order, as when every candidate is scored in place.
+// runs over the atoms in order, as when every candidate is scored in place.  An
+// entry is the step index, with kCandBumped set when the candidate is listed
+// although it bumps (no-pruning mode): it is scored but cannot win.
 // Inside: every candidate position lies in [0, n-2] on every axis.
 template <int P, bool Inside>
 __device__ __forceinline__ u64 score_free(int nfree, const uint16_t *cand, const float4 *rec,
                                           int m, const float2 *tors, const Tri &tr) {
     const int lane = lane_id();
     int kp[P];
+    bool ok[P];
     float2 csp[P];
     float acc[P];
 #pragma unroll
     for (int p = 0; p < P; ++p) {
         const int idx = lane + 64 * p;
-        kp[p] = cand[idx < nfree ? idx : 0];
+        const int e = cand[idx < nfree ? idx : 0];
+        kp[p] = e & (kCandBumped - 1);
+        ok[p] = idx < nfree && !(e & kCandBumped);
         csp[p] = tors[kp[p]];
         acc[p] = 0.f;
     }
@@ -591,7 +599,7 @@ __device__ __forceinline__ u64 score_free(int nfree, const uint16_t *cand, const
     u64 best = 0ull;
 #pragma unroll
     for (int p = 0; p < P; ++p) {
-        const u64 key = lane + 64 * p < nfree ? make_key(acc[p], (uint32_t)kp[p]) : 0ull;
+        const u64 key = ok[p] ? make_key(acc[p], (uint32_t)kp[p]) : 0ull;
         best = key > best ? key : best;
     }
     return best;
@@ -692,8 +700,9 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
             const float aq = 2.0f * fmaf(dx, r1.x, fmaf(dy, r1.y, dz * r1.z));
             const float bq = 2.0f * fmaf(dx, r2.x, fmaf(dy, r2.y, dz * r2.z));
             const float e = cq - lim_in;
-            u64 bal = elm & (__builtin_amdgcn_ballot_w64(e < 0.0f) |
-                             __builtin_amdgcn_ballot_w64(e * e < fmaf(aq, aq, bq * bq)));
+            u64 bal = sa.prune ? elm & (__builtin_amdgcn_ballot_w64(e < 0.0f) |
+                                        __builtin_amdgcn_ballot_w64(e * e < fmaf(aq, aq, bq * bq)))
+                               : elm;
             while (bal != 0ull) {
                 const int src = __ffsll((long long)bal) - 1;
                 bal &= bal - 1ull;
@@ -706,17 +715,19 @@ __device__ int torsion_decide(Pose<NS> &Y, int n, const u64 *mrow, int a, int b,
         }
     }
     // Only the bump-free candidates are scored (on the paper's workloads more than
-    // half are bumped): list them for this wave, then score the list.
+    // half are bumped): list them for this wave, then score the list.  Without
+    // pruning every candidate is listed and scored, the bumped ones flagged.
     int nfree = 0;
 #pragma unroll
     for (int c = 0; c < C; ++c) {
         const int k = sp.first() + lane + sp.stride() * c;
-        const bool fr = k < sa.T && !((bumped[c] >> lane) & 1ull);
-        const u64 bm = __ballot(fr);
-        if (fr)
+        const bool bmp = (bumped[c] >> lane) & 1ull;
+        const bool listed = k < sa.T && (!sa.prune || !bmp);
+        const u64 bm = __ballot(listed);
+        if (listed)
             cand[nfree + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bm >> 32),
                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)bm, 0u))] =
-                (uint16_t)k;
+                (uint16_t)(bmp ? k | kCandBumped : k);
         nfree += __popcll(bm);
     }
     wave_lds_sync();

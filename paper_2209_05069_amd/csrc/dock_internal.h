@@ -45,6 +45,7 @@ struct GridArgs {
 
 struct SearchArgs {
     int R, T, P, A, K, final_align, bmin;
+    int prune;             // 1: prune the bump check and score only bump-free candidates
     float bump2g;          // (bump_dist / spacing)^2, grid units
     float dedup2;          // dedup_rmsd^2, Angstrom^2
     const float4 *smat;    // [R][3] start rotation rows (x,y,z,0)

@@ -81,6 +81,8 @@ struct Ticket {
     long long A = 0, trace_len = 0;
     void *pinned = nullptr;          // pinned inputs followed by the results
     void *host_stage = nullptr;      // results part of `pinned`
+    size_t dev_bytes = 0;            // device memory held until the ticket retires
+    hipStream_t stream = nullptr;    // submit stream the request runs on
     size_t stage_bytes = 0;
     // offsets of the result arrays inside host_stage
     size_t o_best, o_np, o_st, o_ps, o_pr, o_xyz, o_rs, o_tr, o_ft;
@@ -104,6 +106,9 @@ struct dock_ctx {
     std::map<uint64_t, Ticket> tickets;
     uint64_t next_ticket = 1;
     size_t reserve_bytes = (size_t)1 << 30;
+    size_t budget = 0;         // dock_submit admission budget (0: free memory less the reserve)
+    size_t inflight = 0;       // device bytes of admitted tickets not yet retired
+    std::map<hipStream_t, int> stream_tickets;  // tickets in flight per submit stream
     bool timing = false;
     // Batched launch sequences seen once (eager) and captured as graphs when they
     // repeat with identical arguments.
@@ -111,7 +116,8 @@ struct dock_ctx {
     std::map<std::string, hipGraphExec_t> graphs;
     std::vector<hipStream_t> plain_streams;  // plain form: ligands round-robin over these
     std::vector<hipEvent_t> plain_events;
-    std::vector<std::array<hipEvent_t, 4>> marks;  // per call: start, after prep, after dock, end
+    // per call: start, after prep, after the alignment kernels, after dock, end
+    std::vector<std::array<hipEvent_t, 5>> marks;
 };
 
 namespace {
@@ -133,6 +139,7 @@ int check_params(const dock_params *p) {
     if (!(p->bump_dist >= 0.f) || !std::isfinite(p->bump_dist)) return fail(DOCK_EINVAL, "bump_dist must be finite and >= 0");
     if (!(p->dedup_rmsd >= 0.f) || !std::isfinite(p->dedup_rmsd)) return fail(DOCK_EINVAL, "dedup_rmsd must be finite and >= 0");
     if (p->mode != DOCK_MODE_BATCHED && p->mode != DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "unknown mode");
+    if (p->bump_prune != 0 && p->bump_prune != 1) return fail(DOCK_EINVAL, "bump_prune must be 0 or 1");
     if (!p->start_quat) return fail(DOCK_EINVAL, "start_quat is NULL");
     for (int r = 0; r < p->restarts; ++r) {
         double s = 0;
@@ -259,6 +266,10 @@ WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trac
     return w;
 }
 
+// A workspace grows to a quarter more than asked, so that slightly larger later
+// calls reuse it.
+size_t ws_grown_bytes(size_t bytes) { return bytes + bytes / 4; }
+
 int get_workspace(dock_ctx *c, hipStream_t s, size_t bytes, void **out) {
     Workspace &w = c->ws[s];
     if (w.bytes < bytes) {
@@ -268,7 +279,7 @@ int get_workspace(dock_ctx *c, hipStream_t s, size_t bytes, void **out) {
             w.base = nullptr;
             w.bytes = 0;
         }
-        const size_t nb = bytes + bytes / 4;
+        const size_t nb = ws_grown_bytes(bytes);
         if (hipMalloc(&w.base, nb) != hipSuccess) {
             w.base = nullptr;
             if (hipMalloc(&w.base, bytes) != hipSuccess) {
@@ -283,6 +294,48 @@ int get_workspace(dock_ctx *c, hipStream_t s, size_t bytes, void **out) {
     }
     *out = w.base;
     return DOCK_OK;
+}
+
+// Device layout of a dock_submit request: the library copy (inputs, the same
+// layout as the pinned staging buffer) followed by the results; t receives the
+// result offsets.
+struct SubmitLayout {
+    size_t i_ao, i_xyz, i_ty, i_bo, i_b, i_ro, i_rb, i_rm, inputs, results;
+};
+
+SubmitLayout submit_layout(const dock_library *lib, const dock_params *p, const dock_results *o,
+                           Ticket *t) {
+    SubmitLayout sl{};
+    const int L = lib->n_ligands;
+    const long long A = lib->n_atoms_total, Nb = lib->n_bonds_total, Nr = lib->n_rot_total;
+    const int K = p->top_k, R = p->restarts;
+    const long long trace_len = o->trace ? (long long)R * (L + (long long)p->sweep_passes * Nr) : 0;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+    sl.i_ao = take((size_t)(L + 1) * 4);
+    sl.i_xyz = take((size_t)A * 12);
+    sl.i_ty = take((size_t)A);
+    sl.i_bo = take((size_t)(L + 1) * 4);
+    sl.i_b = take((size_t)Nb * 8);
+    sl.i_ro = take((size_t)(L + 1) * 4);
+    sl.i_rb = take((size_t)Nr * 8);
+    sl.i_rm = take((size_t)Nr * lib->mask_words * 8);
+    sl.inputs = off;
+    t->L = L; t->K = K; t->R = R; t->A = A; t->trace_len = trace_len;
+    size_t so = 0;
+    auto stake = [&](size_t b) { size_t r = so; so += align256(b); return r; };
+    t->o_best = stake((size_t)L * 4);
+    t->o_np = stake((size_t)L * 4);
+    t->o_st = stake((size_t)L * 4);
+    t->o_ps = stake((size_t)L * K * 4);
+    t->o_pr = stake((size_t)L * K * 4);
+    t->o_xyz = stake((size_t)A * K * 12);
+    t->o_rs = stake(o->restart_score ? (size_t)L * R * 4 : 0);
+    t->o_tr = stake((size_t)trace_len * 2);
+    t->o_ft = stake(o->final_trace ? (size_t)L * K * 2 : 0);
+    t->stage_bytes = so;
+    sl.results = so;
+    return sl;
 }
 
 int occupancy(dock_ctx *c, const std::string &key, int v) {
@@ -307,7 +360,7 @@ constexpr int kPlainStreams = 4;
 // back first (this form is synchronous with respect to the host anyway).
 int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const SearchArgs &sa,
                   const LibArgs &la, const WorkArgs &wa, const OutArgs &oa,
-                  const std::array<hipEvent_t, 4> &ev, hipStream_t s) {
+                  const std::array<hipEvent_t, 5> &ev, hipStream_t s) {
     const int L = lib->n_ligands;
     std::vector<int32_t> ao(L + 1);
     HIP_TRY(hipMemcpyAsync(ao.data(), lib->atom_off, sizeof(int32_t) * (L + 1),
@@ -323,6 +376,7 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
     }
     if (c->timing) HIP_TRY(hipEventRecord(ev[0], s));
     if (c->timing) HIP_TRY(hipEventRecord(ev[1], s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[2], s));  // no separate alignment phase
     hipEvent_t go;
     HIP_TRY(hipEventCreateWithFlags(&go, hipEventDisableTiming));
     HIP_TRY(hipEventRecord(go, s));
@@ -341,8 +395,8 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
         HIP_TRY(hipStreamWaitEvent(s, c->plain_events[i], 0));
     }
     HIP_TRY(hipEventDestroy(go));
-    if (c->timing) HIP_TRY(hipEventRecord(ev[2], s));
     if (c->timing) HIP_TRY(hipEventRecord(ev[3], s));
+    if (c->timing) HIP_TRY(hipEventRecord(ev[4], s));
     return DOCK_OK;
 }
 
@@ -369,6 +423,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     sa.K = p->top_k;
     sa.final_align = p->final_align;
     sa.bmin = p->bump_min_bonds;
+    sa.prune = p->bump_prune;
     {
         const double bg = (double)p->bump_dist * (double)g.inv_h;
         sa.bump2g = (float)(bg * bg);
@@ -413,7 +468,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     oa.rscore_user = o->restart_score;
     oa.ftrace = o->final_trace;
 
-    std::array<hipEvent_t, 4> ev{};
+    std::array<hipEvent_t, 5> ev{};
     if (c->timing) {
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         c->marks.push_back(ev);
@@ -443,12 +498,13 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         if (marks) HIP_TRY(hipEventRecord(ev[1], s));
         for (int bin = 0; bin < kNumBins; ++bin)
             HIP_TRY(launch_align(bin, align_blocks[bin], c->lds_arena, g, sa, la, wa, s));
-        for (int bin = 0; bin < kNumBins; ++bin)
-            HIP_TRY(launch_dock(bin, dock_blocks[bin], kDockWaves, g, sa, la, wa, s));
         if (marks) HIP_TRY(hipEventRecord(ev[2], s));
         for (int bin = 0; bin < kNumBins; ++bin)
-            HIP_TRY(launch_final(bin, final_blocks[bin], kFinalWaves, g, sa, la, wa, oa, -1, s));
+            HIP_TRY(launch_dock(bin, dock_blocks[bin], kDockWaves, g, sa, la, wa, s));
         if (marks) HIP_TRY(hipEventRecord(ev[3], s));
+        for (int bin = 0; bin < kNumBins; ++bin)
+            HIP_TRY(launch_final(bin, final_blocks[bin], kFinalWaves, g, sa, la, wa, oa, -1, s));
+        if (marks) HIP_TRY(hipEventRecord(ev[4], s));
         return DOCK_OK;
     };
     if (c->timing || s == nullptr) return sequence(c->timing);
@@ -543,7 +599,7 @@ extern "C" {
 
 const char *dock_last_error(void) { return g_err.c_str(); }
 
-int dock_create(int device, dock_ctx **out) {
+int dock_create(int device, uint64_t hbm_budget_bytes, dock_ctx **out) {
     if (!out) return fail(DOCK_EINVAL, "out is NULL");
     *out = nullptr;
     int n = 0;
@@ -558,6 +614,7 @@ int dock_create(int device, dock_ctx **out) {
     if (!c) return fail(DOCK_ENOMEM, "context allocation failed");
     c->device = device;
     c->num_cu = prop.multiProcessorCount;
+    c->budget = (size_t)hbm_budget_bytes;
     c->lds_arena = (int)std::min<size_t>(prop.sharedMemPerBlock, (size_t)160 * 1024);
     for (int i = 0; i < kSubmitStreams; ++i) {
         hipStream_t t = nullptr;
@@ -713,39 +770,47 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
     HIP_TRY(hipSetDevice(c->device));
     const long long A = lib->n_atoms_total, Nb = lib->n_bonds_total, Nr = lib->n_rot_total;
-    const int K = p->top_k, R = p->restarts;
-    const long long trace_len = o->trace ? (long long)R * (L + (long long)p->sweep_passes * Nr) : 0;
-    // device copy of the library and of the results, one allocation
-    size_t off = 0;
-    auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
-    const size_t i_ao = take((size_t)(L + 1) * 4), i_xyz = take((size_t)A * 12), i_ty = take((size_t)A),
-                 i_bo = take((size_t)(L + 1) * 4), i_b = take((size_t)Nb * 8), i_ro = take((size_t)(L + 1) * 4),
-                 i_rb = take((size_t)Nr * 8), i_rm = take((size_t)Nr * lib->mask_words * 8);
     Ticket t;
-    t.L = L; t.K = K; t.R = R; t.A = A; t.trace_len = trace_len;
-    size_t so = 0;
-    auto stake = [&](size_t b) { size_t r = so; so += align256(b); return r; };
-    t.o_best = stake((size_t)L * 4);
-    t.o_np = stake((size_t)L * 4);
-    t.o_st = stake((size_t)L * 4);
-    t.o_ps = stake((size_t)L * K * 4);
-    t.o_pr = stake((size_t)L * K * 4);
-    t.o_xyz = stake((size_t)A * K * 12);
-    t.o_rs = stake(o->restart_score ? (size_t)L * R * 4 : 0);
-    t.o_tr = stake((size_t)trace_len * 2);
-    t.o_ft = stake(o->final_trace ? (size_t)L * K * 2 : 0);
-    t.stage_bytes = so;
+    const SubmitLayout sl = submit_layout(lib, p, o, &t);
+    const size_t off = sl.inputs, so = sl.results;
+    const size_t i_ao = sl.i_ao, i_xyz = sl.i_xyz, i_ty = sl.i_ty, i_bo = sl.i_bo, i_b = sl.i_b,
+                 i_ro = sl.i_ro, i_rb = sl.i_rb, i_rm = sl.i_rm;
     const size_t dev_bytes = off + so;
-    // admission: library + results + workspace must fit in free memory less a reserve
+    // admission: library + results + workspace growth must fit in the budget next to
+    // the admitted work (or, without a budget, in free memory less a reserve)
     hipStream_t s_pick = nullptr;
     {
         const WsLayout wl = ws_layout(lib, p, o->trace != nullptr);
-        size_t freeb = 0, totalb = 0;
-        HIP_TRY(hipMemGetInfo(&freeb, &totalb));
         s_pick = c->submit_streams[c->next_submit % c->submit_streams.size()];
         const size_t have_ws = c->ws.count(s_pick) ? c->ws[s_pick].bytes : 0;
-        const size_t need = dev_bytes + (wl.total > have_ws ? wl.total : 0);
-        if (need + c->reserve_bytes > freeb) return fail(DOCK_EAGAIN, "not enough free device memory");
+        const size_t growth = wl.total > have_ws ? ws_grown_bytes(wl.total) - have_ws : 0;
+        const size_t need = dev_bytes + growth;
+        if (c->budget > 0) {
+            size_t held = c->inflight;
+            for (auto u : c->submit_streams) held += c->ws.count(u) ? c->ws[u].bytes : 0;
+            if (held + need > c->budget) {
+                // release the workspaces of submit streams with nothing in flight
+                for (auto u : c->submit_streams) {
+                    if (c->stream_tickets[u] > 0 || !c->ws.count(u) || !c->ws[u].base) continue;
+                    HIP_TRY(hipStreamSynchronize(u));
+                    HIP_TRY(hipFree(c->ws[u].base));
+                    held -= c->ws[u].bytes;
+                    c->ws[u].base = nullptr;
+                    c->ws[u].bytes = 0;
+                }
+            }
+            const size_t have_now = c->ws.count(s_pick) ? c->ws[s_pick].bytes : 0;
+            const size_t need_now = dev_bytes + (wl.total > have_now ? ws_grown_bytes(wl.total) - have_now : 0);
+            if (held + need_now > c->budget)
+                return fail(DOCK_EAGAIN, "request does not fit in the device-memory budget now (" +
+                                             std::to_string(held) + " B held, " +
+                                             std::to_string(need_now) + " B needed, budget " +
+                                             std::to_string(c->budget) + " B)");
+        } else {
+            size_t freeb = 0, totalb = 0;
+            HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+            if (need + c->reserve_bytes > freeb) return fail(DOCK_EAGAIN, "not enough free device memory");
+        }
     }
     hipStream_t s = s_pick;
     c->next_submit += 1;
@@ -823,10 +888,29 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     }
     t.pocket = pocket;
     t.user = *o;
+    t.dev_bytes = dev_bytes;
+    t.stream = s;
+    c->inflight += dev_bytes;
+    c->stream_tickets[s] += 1;
     it->second.busy += 1;
     const uint64_t id = c->next_ticket++;
     c->tickets[id] = t;
     *ticket = id;
+    return DOCK_OK;
+}
+
+int dock_request_bytes(const dock_library *lib, const dock_params *p, const dock_results *o,
+                       uint64_t *bytes) {
+    if (!bytes) return fail(DOCK_EINVAL, "bytes is NULL");
+    int rc = check_params(p);
+    if (rc) return rc;
+    rc = check_library_shape(lib);
+    if (rc) return rc;
+    if (!o) return fail(DOCK_EINVAL, "results is NULL");
+    Ticket t;
+    const SubmitLayout sl = submit_layout(lib, p, o, &t);
+    const WsLayout wl = ws_layout(lib, p, o->trace != nullptr);
+    *bytes = (uint64_t)(sl.inputs + sl.results + ws_grown_bytes(wl.total));
     return DOCK_OK;
 }
 
@@ -848,6 +932,8 @@ static int finish_ticket(dock_ctx *c, std::map<uint64_t, Ticket>::iterator it) {
     }
     hipEventDestroy(t.done);
     hipHostFree(t.pinned);
+    c->inflight -= t.dev_bytes < c->inflight ? t.dev_bytes : c->inflight;
+    c->stream_tickets[t.stream] -= 1;
     auto pk = c->pockets.find(t.pocket);
     if (pk != c->pockets.end() && pk->second.busy > 0) pk->second.busy -= 1;
     c->tickets.erase(it);
@@ -891,12 +977,14 @@ int dock_get_timing(dock_ctx *c, dock_timing *out) {
     HIP_TRY(hipSetDevice(c->device));
     dock_timing t{};
     for (auto &m : c->marks) {
-        HIP_TRY(hipEventSynchronize(m[3]));
-        float a = 0.f, b = 0.f, d = 0.f;
+        HIP_TRY(hipEventSynchronize(m[4]));
+        float a = 0.f, al = 0.f, b = 0.f, d = 0.f;
         HIP_TRY(hipEventElapsedTime(&a, m[0], m[1]));
-        HIP_TRY(hipEventElapsedTime(&b, m[1], m[2]));
-        HIP_TRY(hipEventElapsedTime(&d, m[2], m[3]));
+        HIP_TRY(hipEventElapsedTime(&al, m[1], m[2]));
+        HIP_TRY(hipEventElapsedTime(&b, m[1], m[3]));
+        HIP_TRY(hipEventElapsedTime(&d, m[3], m[4]));
         t.prep_ms += a;
+        t.align_ms += al;
         t.dock_ms += b;
         t.final_ms += d;
         t.calls += 1;

@@ -47,8 +47,8 @@ class Params(ctypes.Structure):
                 ("sweep_passes", ctypes.c_int32), ("align_steps", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("final_align", ctypes.c_int32),
                 ("bump_min_bonds", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("bump_dist", ctypes.c_float), ("dedup_rmsd", ctypes.c_float),
-                ("start_quat", P)]
+                ("bump_prune", ctypes.c_int32), ("bump_dist", ctypes.c_float),
+                ("dedup_rmsd", ctypes.c_float), ("start_quat", P)]
 
 
 class Results(ctypes.Structure):
@@ -59,13 +59,14 @@ class Results(ctypes.Structure):
 
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("dock_ms", ctypes.c_double),
-                ("final_ms", ctypes.c_double), ("calls", ctypes.c_int64),
+                ("align_ms", ctypes.c_double), ("final_ms", ctypes.c_double),
+                ("calls", ctypes.c_int64),
                 ("scored_samples", ctypes.c_int64)]
 
 
 EXPORTS = ["dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
            "dock_ligands_batch", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
-           "dock_set_timing", "dock_submit", "dock_wait"]
+           "dock_request_bytes", "dock_set_timing", "dock_submit", "dock_wait"]
 
 _lib = None
 
@@ -80,7 +81,7 @@ def lib():
         # makes libdock.so bind to that same runtime instead of a second copy.
         import torch  # noqa: F401
         L = ctypes.CDLL(LIBPATH)
-        L.dock_create.argtypes = [ctypes.c_int, ctypes.POINTER(P)]
+        L.dock_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.POINTER(P)]
         L.dock_destroy.argtypes = [P]
         L.dock_last_error.restype = ctypes.c_char_p
         L.dock_pocket_load.argtypes = [P, ctypes.POINTER(GridDesc), ctypes.POINTER(ctypes.c_int32)]
@@ -91,6 +92,8 @@ def lib():
                                   ctypes.POINTER(Params), ctypes.POINTER(Results),
                                   ctypes.POINTER(ctypes.c_uint64)]
         L.dock_poll.argtypes = [P, ctypes.c_uint64, ctypes.POINTER(ctypes.c_int32)]
+        L.dock_request_bytes.argtypes = [ctypes.POINTER(Library), ctypes.POINTER(Params),
+                                         ctypes.POINTER(Results), ctypes.POINTER(ctypes.c_uint64)]
         L.dock_wait.argtypes = [P, ctypes.c_uint64]
         L.dock_set_timing.argtypes = [P, ctypes.c_int]
         L.dock_get_timing.argtypes = [P, ctypes.POINTER(Timing)]
@@ -108,9 +111,9 @@ def dock_last_error() -> str:
     return lib().dock_last_error().decode()
 
 
-def dock_create(device: int = 0):
+def dock_create(device: int = 0, hbm_budget_bytes: int = 0):
     h = P()
-    _check(lib().dock_create(device, ctypes.byref(h)))
+    _check(lib().dock_create(device, int(hbm_budget_bytes), ctypes.byref(h)))
     return h
 
 
@@ -133,7 +136,8 @@ def dock_pocket_unload(ctx, pocket_id: int):
 
 
 DEFAULT_PARAMS = dict(torsion_steps=256, sweep_passes=3, align_steps=30, top_k=30, final_align=1,
-                      bump_min_bonds=4, bump_dist=2.0, dedup_rmsd=2.0, mode=DOCK_MODE_BATCHED)
+                      bump_min_bonds=4, bump_dist=2.0, dedup_rmsd=2.0, mode=DOCK_MODE_BATCHED,
+                      bump_prune=1)
 
 
 class SearchParams:
@@ -152,7 +156,8 @@ class SearchParams:
         self.values = p
         self.s = Params(len(self.quat), p["torsion_steps"], p["sweep_passes"], p["align_steps"],
                         p["top_k"], p["final_align"], p["bump_min_bonds"], p["mode"],
-                        p["bump_dist"], p["dedup_rmsd"], ctypes.c_void_p(self.quat.ctypes.data))
+                        p["bump_prune"], p["bump_dist"], p["dedup_rmsd"],
+                        ctypes.c_void_p(self.quat.ctypes.data))
 
     def __getattr__(self, k):
         v = self.__dict__.get("values")
@@ -303,6 +308,15 @@ def dock_submit(ctx, pocket: int, host_lib, params: SearchParams, res: HostResul
     return t.value
 
 
+def dock_request_bytes(host_lib, params: SearchParams, res: HostResults) -> int:
+    """Device bytes a dock_submit of this request needs (see include/dock.h)."""
+    s, arrs = host_library_struct(host_lib)
+    b = ctypes.c_uint64()
+    _check(lib().dock_request_bytes(ctypes.byref(s), ctypes.byref(params.s), ctypes.byref(res.s),
+                                    ctypes.byref(b)))
+    return b.value
+
+
 def dock_poll(ctx, ticket: int) -> bool:
     d = ctypes.c_int32()
     _check(lib().dock_poll(ctx, ticket, ctypes.byref(d)))
@@ -320,8 +334,8 @@ def dock_set_timing(ctx, enable: bool):
 def dock_get_timing(ctx) -> dict:
     t = Timing()
     _check(lib().dock_get_timing(ctx, ctypes.byref(t)))
-    return dict(prep_ms=t.prep_ms, dock_ms=t.dock_ms, final_ms=t.final_ms, calls=t.calls,
-                scored_samples=t.scored_samples)
+    return dict(prep_ms=t.prep_ms, dock_ms=t.dock_ms, align_ms=t.align_ms, final_ms=t.final_ms,
+                calls=t.calls, scored_samples=t.scored_samples)
 
 
 def trace_offset(l, R, P, rot_off):

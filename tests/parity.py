@@ -15,6 +15,9 @@ Pass/fail bar (FP32 GPU vs FP64 oracle):
   * final scores within SCORE_REL * max(1, |S|); restart scores likewise;
   * final poses within POSE_RMSD Angstrom RMSD.
 """
+import json
+import os
+
 import numpy as np
 
 from oracle import oracle as O
@@ -100,3 +103,12 @@ def check_ligand(grid, lig, quats, params, g, stats=None):
                                      max((rmsd(g["pose_xyz"][s], o["pose_xyz"][s])
                                           for s in range(len(fs))), default=0.0))
     return o
+
+
+def report(label, stats):
+    """Append one JSON line of parity statistics to the file named by the
+    DOCK_PARITY_REPORT environment variable (nothing when it is unset)."""
+    path = os.environ.get("DOCK_PARITY_REPORT")
+    if path:
+        with open(path, "a") as f:
+            f.write(json.dumps(dict(label=label, **stats)) + "\n")

@@ -36,8 +36,8 @@ def test_every_declared_symbol_is_exported(L):
 
 def test_null_arguments_are_rejected_with_a_message(L):
     L.dock_last_error.restype = ctypes.c_char_p
-    L.dock_create.argtypes = [ctypes.c_int, ctypes.c_void_p]
-    assert L.dock_create(0, None) == -1
+    L.dock_create.argtypes = [ctypes.c_int, ctypes.c_uint64, ctypes.c_void_p]
+    assert L.dock_create(0, 0, None) == -1
     assert b"NULL" in L.dock_last_error()
     L.dock_destroy.argtypes = [ctypes.c_void_p]
     assert L.dock_destroy(None) == -1
@@ -67,3 +67,27 @@ def test_header_structs_match_binding_layout():
                 nm = re.sub(r"\[.*\]", "", nm)
                 fields.append(nm)
         assert fields == [f[0] for f in cls._fields_], (struct, fields)
+
+
+def test_request_bytes_needs_no_device():
+    """dock_request_bytes reads sizes only: it answers on a machine without a GPU,
+    grows with the library and with the optional outputs, and checks its params."""
+    import numpy as np
+    import synth
+    from paper_2209_05069_amd import dock
+    lib = synth.library_uniform(5, 6, (10, 30), (1, 4))
+    big = synth.library_uniform(5, 60, (10, 30), (1, 4))
+    q = synth.start_quats(5, 8)
+    p = dock.SearchParams(q, torsion_steps=16, top_k=4)
+    b_small = dock.dock_request_bytes(lib, p, dock.HostResults(6, int(lib.atom_off[-1]),
+                                                               int(lib.rot_off[-1]), p))
+    b_big = dock.dock_request_bytes(big, p, dock.HostResults(60, int(big.atom_off[-1]),
+                                                             int(big.rot_off[-1]), p))
+    b_trace = dock.dock_request_bytes(lib, p, dock.HostResults(
+        6, int(lib.atom_off[-1]), int(lib.rot_off[-1]), p, restart_scores=True))
+    assert 0 < b_small < b_big and b_small < b_trace
+    bad = dock.SearchParams(q, torsion_steps=16, top_k=4, bump_prune=2)
+    with pytest.raises(dock.DockError):
+        dock.dock_request_bytes(lib, bad, dock.HostResults(6, int(lib.atom_off[-1]),
+                                                           int(lib.rot_off[-1]), bad))
+    assert np.isfinite(b_small)

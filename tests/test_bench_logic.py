@@ -5,6 +5,7 @@ import os
 import subprocess
 import sys
 
+import numpy as np
 import pytest
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -21,15 +22,36 @@ def _source_sha():
 
 
 def test_traffic_only_for_the_measured_source_and_workload():
-    s = dict(synth.CONFIGS[2]["search"])
-    L = synth.CONFIGS[2]["ligands"]["L"]
-    expect = bench.TRAFFIC_BYTES_PER_STEP if _source_sha() == bench.TRAFFIC_SOURCE_SHA else None
-    assert bench.kernel_traffic(2, L, s) == expect
-    # any other search, library size or config: no byte figure
-    assert bench.kernel_traffic(2, L, dict(s, torsion_steps=10)) is None
-    assert bench.kernel_traffic(2, L - 1, s) is None
-    assert bench.kernel_traffic(3, synth.CONFIGS[3]["ligands"]["L"],
-                                dict(synth.CONFIGS[3]["search"])) is None
+    s3 = dict(synth.CONFIGS[3]["search"])
+    L3 = synth.CONFIGS[3]["ligands"]["L"]
+    saved = dict(bench.TRAFFIC)
+    try:
+        bench.TRAFFIC.clear()
+        bench.TRAFFIC[(3, 256, L3)] = ("k_dock", _source_sha(), 1.0e11)
+        assert bench.kernel_traffic(3, L3, s3, "k_dock") == 1.0e11
+        # another kernel, search, library size, config or kernel source: no byte figure
+        assert bench.kernel_traffic(3, L3, s3, "k_align") is None
+        assert bench.kernel_traffic(3, L3, dict(s3, torsion_steps=10), "k_dock") is None
+        assert bench.kernel_traffic(3, L3 - 1, s3, "k_dock") is None
+        assert bench.kernel_traffic(2, synth.CONFIGS[2]["ligands"]["L"],
+                                    dict(synth.CONFIGS[2]["search"]), "k_dock") is None
+        bench.TRAFFIC[(3, 256, L3)] = ("k_dock", "0" * 16, 1.0e11)
+        assert bench.kernel_traffic(3, L3, s3, "k_dock") is None
+    finally:
+        bench.TRAFFIC.clear()
+        bench.TRAFFIC.update(saved)
+
+
+def test_stratified_order_is_a_permutation_taking_cells_in_turn():
+    lib = synth.library_uniform(11, 400, (20, 100), (0, 20))
+    order = bench.stratified_order(lib, 2209)
+    assert sorted(order) == list(range(lib.n_ligands))
+    assert order == bench.stratified_order(lib, 2209)
+    # the first 8 ligands come from 8 different (atom quartile, bond half) cells
+    n, B = lib.n_atoms(), lib.n_rot()
+    qa = np.quantile(n, [0.25, 0.5, 0.75])
+    cell = np.searchsorted(qa, n, side="right") * 2 + (B > np.median(B))
+    assert len(set(cell[order[:8]])) == 8
 
 
 def test_workload_counts_small_library():

@@ -52,6 +52,7 @@ def check_all(D, pk, lib, quats, h, params, ligands=None, label=""):
         assert g["status"] == 0, (l, g["status"])
         parity.check_ligand(grid, O.ligand_from_library(lib, l), quats, params, g, stats)
     print(f"[parity {label}] {stats}", flush=True)
+    parity.report(label, stats)
     return stats
 
 
@@ -334,3 +335,122 @@ def test_graph_replays_match_eager(D, ctx):
         D.dock_ligands_batch(ctx, pid, do, params, ro)          # other eager work between
         torch.cuda.synchronize()
     D.dock_pocket_unload(ctx, pid)
+
+
+def test_production_parameters_every_slot_count(D, ctx):
+    """The paper-scale search (A = 30, T = 256, P = 3, K = 30) on the 96^3 x 4
+    pocket, with 32 restarts (one whole alignment group), on ligands that take
+    every slot count of the kernels: 30 atoms (one 64-lane slot), 75 and 100
+    (two), 140 (three) and 200 (four), with 12 to 30 rotatable bonds; both forms
+    against the oracle."""
+    c2 = synth.CONFIGS[2]
+    pk = synth.pocket_gaussians(synth.MASTER_SEED + 2, **c2["pocket"])
+    lib = synth.library_from_sizes(308, [30, 75, 100, 140, 200], [12, 20, 20, 30, 30])
+    q = synth.start_quats(synth.MASTER_SEED + 2, 32)
+    s = dict(c2["search"], restarts=32)
+    for mode, label in ((D.DOCK_MODE_BATCHED, "batched"), (D.DOCK_MODE_PLAIN, "plain")):
+        print(f"[case] production parameters, slots 1..4, {label}", flush=True)
+        h, params = run_batch(D, ctx, pk, lib, q, mode=mode, **s)
+        check_all(D, pk, lib, q, h, params, label=f"production-{label}")
+
+
+def test_no_pruning_ablation_selects_the_same_steps(D, ctx):
+    """bump_prune = 0 tests every eligible pair against every candidate and scores
+    every candidate, applying the bump verdict afterwards: the decisions and all
+    outputs are bit-identical to the pruned path, in both forms, and pass the
+    oracle; the kernels report every candidate as scored."""
+    pk = synth.pocket_gaussians(309, 4, 48, 0.5, 60, 6.0)
+    lib = synth.library_from_sizes(309, [20, 45, 70, 130], [3, 8, 12, 20])
+    q = synth.start_quats(309, 8)
+    s = dict(torsion_steps=64, sweep_passes=2, align_steps=10, top_k=4, dedup_rmsd=1.0)
+    for mode, label in ((D.DOCK_MODE_BATCHED, "batched"), (D.DOCK_MODE_PLAIN, "plain")):
+        print(f"[case] no-pruning ablation, {label}", flush=True)
+        counts = {}
+        out = {}
+        for prune in (1, 0):
+            D.dock_set_timing(ctx, True)
+            D.dock_get_timing(ctx)
+            out[prune], params = run_batch(D, ctx, pk, lib, q, mode=mode, bump_prune=prune, **s)
+            counts[prune] = D.dock_get_timing(ctx)["scored_samples"]
+            D.dock_set_timing(ctx, False)
+        for k in out[1]:
+            if out[1][k] is not None:
+                np.testing.assert_array_equal(out[1][k], out[0][k], err_msg=f"{label}:{k}")
+        m = [bin(int(w)).count("1") for w in lib.rot_mask.reshape(-1)]
+        all_cand = q.shape[0] * s["sweep_passes"] * s["torsion_steps"] * sum(m)
+        print(f"[scored] {label} pruned {counts[1]}, unpruned {counts[0]} of {all_cand}", flush=True)
+        assert counts[0] == all_cand and counts[1] < all_cand
+        check_all(D, pk, lib, q, out[0], params, label=f"no-pruning-{label}")
+
+
+def test_submit_admission_budget(D):
+    """A context with a device-memory budget admits a request that fits, refuses a
+    second one while the first holds its memory (DOCK_EAGAIN, nothing enqueued),
+    and admits it once the first has retired; both results equal the
+    device-resident batch."""
+    pk, lib, q, s = synth.config(1)
+    params = D.SearchParams(q, **s)
+    need = D.dock_request_bytes(lib, params, D.HostResults(
+        lib.n_ligands, int(lib.atom_off[-1]), int(lib.rot_off[-1]), params))
+    print(f"[case] admission budget, request needs {need} B", flush=True)
+    ref_ctx = D.dock_create(0)
+    try:
+        ref, _ = run_batch(D, ref_ctx, pk, lib, q, **s)
+    finally:
+        D.dock_destroy(ref_ctx)
+    c = D.dock_create(0, hbm_budget_bytes=need + need // 2)
+    try:
+        pid = D.dock_pocket_load(c, pk.values, pk.spacing, pk.origin)
+        mk = lambda: D.HostResults(lib.n_ligands, int(lib.atom_off[-1]), int(lib.rot_off[-1]),
+                                   params)
+        ra, rb = mk(), mk()
+        ta = D.dock_submit(c, pid, lib, params, ra)
+        with pytest.raises(D.DockError) as ei:
+            D.dock_submit(c, pid, lib, params, rb)
+        assert ei.value.code == D.DOCK_EAGAIN
+        D.dock_wait(c, ta)
+        tb = D.dock_submit(c, pid, lib, params, rb)
+        D.dock_wait(c, tb)
+        for r in (ra, rb):
+            h = r.to_host()
+            for k in ("best_score", "n_poses", "status", "pose_score", "pose_restart", "pose_xyz"):
+                np.testing.assert_array_equal(h[k], ref[k], err_msg=k)
+        D.dock_pocket_unload(c, pid)
+        tiny = D.dock_create(0, hbm_budget_bytes=1)
+        try:
+            pid2 = D.dock_pocket_load(tiny, pk.values, pk.spacing, pk.origin)
+            with pytest.raises(D.DockError) as ei:
+                D.dock_submit(tiny, pid2, lib, params, mk())
+            assert ei.value.code == D.DOCK_EAGAIN
+        finally:
+            D.dock_destroy(tiny)
+    finally:
+        D.dock_destroy(c)
+
+
+def test_serving_loop_maps_results_to_requests(D, ctx):
+    """The serving loop (per-pocket buckets over dock_submit/dock_poll) returns,
+    for every request, the best score the device-resident batch gives for the
+    same ligand and pocket."""
+    from paper_2209_05069_amd import serve as S
+    pockets = [synth.pocket_gaussians(370 + p, 4, 32, 0.5, 40, 4.0) for p in range(3)]
+    lib = synth.library_uniform(370, 40, (12, 40), (0, 6))
+    q = synth.start_quats(370, 8)
+    s = dict(torsion_steps=32, sweep_passes=1, align_steps=10, top_k=4, dedup_rmsd=1.0)
+    params = D.SearchParams(q, **s)
+    pids = {p: D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+            for p, pk in enumerate(pockets)}
+    rng = np.random.default_rng(370)
+    reqs = [S.Request(i, int(rng.integers(0, 3)), int(rng.integers(0, lib.n_ligands)), 0.0)
+            for i in range(120)]
+    print("[case] serving loop, 120 requests over 3 pockets", flush=True)
+    srv = S.Server(ctx, pids, lib, params, max_batch=16, flush_ms=2.0)
+    r = S.run(srv, reqs, S.poisson_arrivals(2000.0, len(reqs), 370), time_limit_s=60.0)
+    assert r["completed"] == len(reqs)
+    for p in range(3):
+        D.dock_pocket_unload(ctx, pids[p])
+    for p, pk in enumerate(pockets):
+        h, _ = run_batch(D, ctx, pk, lib, q, **s)
+        for req in reqs:
+            if req.pocket == p:
+                assert srv.results[req.rid] == h["best_score"][req.ligand], req
