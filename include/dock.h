@@ -198,6 +198,33 @@ typedef struct {
 int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
                        const dock_params *params, dock_results *out, void *stream);
 
+/* Size of the device scratch array behind dock_ligands_batch_noalloc: 64 MiB,
+ * held on each device the library runs on until the process ends. */
+#define DOCK_NOALLOC_SCRATCH_BYTES (64u << 20)
+
+/* dock_ligands_batch for callers that cannot allocate device memory (code that
+ * runs under stream capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same arguments, kernels and results as dock_ligands_batch with
+ * mode DOCK_MODE_BATCHED, but its tables and workspace live in a fixed
+ * per-device scratch array of DOCK_NOALLOC_SCRATCH_BYTES, so the call allocates
+ * no device memory, captures no graph and records no phase timing.  It enqueues
+ * on `stream` one host-to-device copy of its tables (from host memory the
+ * context keeps) and the kernels.
+ * Limits: DOCK_EINVAL (nothing enqueued) when mode is not DOCK_MODE_BATCHED or
+ * when the request needs more scratch than DOCK_NOALLOC_SCRATCH_BYTES: the
+ * tables (16*3R B of start rotations, 16*3A^2 B of alignment rotations, 8*T B
+ * of torsion (cos, sin), 8*(A rounded up to 32) B of alignment (cos, sin)) plus
+ * the workspace (per atom 32 B of bump-pair rows and 12*top_k B of kept poses;
+ * per ligand 4*R B of restart scores and 32 B of bin lists; 128 B of counters;
+ * and, when out->trace is NULL, 2*R*(L + P*n_rot_total) B of decision trace),
+ * each part rounded up to a multiple of 256 B.
+ * Every call on a device shares that device's array and leaves its contents
+ * there: calls that overlap on one device (different streams or contexts) race
+ * and give wrong results; calls on one stream are ordered by it.  The array's
+ * counters are cleared by the call's own first kernel. */
+int dock_ligands_batch_noalloc(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
+                               const dock_params *params, dock_results *out, void *stream);
+
 /* Asynchronous form on host memory (paper: the batched form's asynchronous
  * interface, Batched Implementation subsection).  The library and params are
  * copied before the call returns; `out` must stay valid until dock_poll reports

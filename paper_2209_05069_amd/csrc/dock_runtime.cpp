@@ -26,6 +26,13 @@
 
 using namespace dockgpu;
 
+// Scratch memory of dock_ligands_batch_noalloc (for callers that cannot
+// allocate device memory): the call's tables and workspace live in this array.
+// Host code never passes the array's name to a kernel or a copy (on the host it
+// is only a stand-in for the symbol); dock_create looks up its address on each
+// device once, and the entry point uses that address.
+static __device__ __align__(256) unsigned char scratch[DOCK_NOALLOC_SCRATCH_BYTES];
+
 namespace {
 
 thread_local std::string g_err;
@@ -41,6 +48,28 @@ int fail(int code, const std::string &msg) {
         if (e_ != hipSuccess)                                                        \
             return fail(DOCK_EDEVICE, std::string(#expr) + ": " + hipGetErrorString(e_)); \
     } while (0)
+
+
+std::mutex g_scratch_mu;
+std::map<int, char *> g_scratch_ptr;  // device -> address of its copy of `scratch`
+
+// Address of `scratch` on `device` (the current device), looked up once.
+int scratch_address(int device, char **out) {
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    auto it = g_scratch_ptr.find(device);
+    if (it == g_scratch_ptr.end()) {
+        void *ptr = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || ptr == nullptr) {
+            (void)hipGetLastError();
+            return fail(DOCK_EDEVICE, std::string("scratch symbol lookup failed: ") +
+                                          hipGetErrorString(e));
+        }
+        it = g_scratch_ptr.emplace(device, (char *)ptr).first;
+    }
+    *out = it->second;
+    return DOCK_OK;
+}
 
 struct Pocket {
     float4 *d_cubes = nullptr;
@@ -73,6 +102,12 @@ struct Tables {
     const float2 *acs = nullptr;
 };
 
+// Host image of a Tables allocation (offsets relative to its start).
+struct TableBlob {
+    std::vector<char> bytes;
+    size_t o_smat = 0, o_amat = 0, o_tors = 0, o_acs = 0;
+};
+
 struct Ticket {
     hipEvent_t done = nullptr;
     int32_t pocket = -1;
@@ -100,6 +135,10 @@ struct dock_ctx {
     int32_t next_pocket = 1;
     std::map<hipStream_t, Workspace> ws;
     std::map<std::string, Tables> tables;
+    // dock_ligands_batch_noalloc: host images of the tables it copied into the
+    // scratch array, kept until destroy so no asynchronous copy outlives its source
+    std::map<std::string, TableBlob> noalloc_tables;
+    char *scratch = nullptr;  // this device's copy of the scratch array
     std::map<std::string, int> occ;
     std::vector<hipStream_t> submit_streams;  // dock_submit: requests round-robin over these
     size_t next_submit = 0;
@@ -182,16 +221,17 @@ int check_results(const dock_results *o, int n_ligands) {
 }
 
 // Start rotations (quaternion -> matrix), alignment rotations R_y(beta_j) R_x(alpha_i),
-// torsion (cos, sin): computed in double, rounded to float.
-int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
+// torsion (cos, sin): computed in double, rounded to float, in one host blob
+// (offsets in `t`, relative to the blob's start).
+std::string tables_key(const dock_params *p) {
+    std::string key((const char *)p->start_quat, sizeof(float) * 4 * (size_t)p->restarts);
+    key += "|" + std::to_string(p->restarts) + "|" + std::to_string(p->align_steps) + "|" +
+           std::to_string(p->torsion_steps);
+    return key;
+}
+
+void make_tables(const dock_params *p, TableBlob *out) {
     const int R = p->restarts, A = p->align_steps, T = p->torsion_steps;
-    std::string key((const char *)p->start_quat, sizeof(float) * 4 * (size_t)R);
-    key += "|" + std::to_string(R) + "|" + std::to_string(A) + "|" + std::to_string(T);
-    auto it = c->tables.find(key);
-    if (it != c->tables.end()) {
-        *out = it->second;
-        return DOCK_OK;
-    }
     const size_t nS = (size_t)R * 3, nA = (size_t)A * A * 3;
     std::vector<float4> smat(nS), amat(nA);
     std::vector<float2> tors(T);
@@ -229,19 +269,42 @@ int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
     }
     const size_t bS = align256(nS * sizeof(float4)), bA = align256(nA * sizeof(float4)),
                  bT = align256((size_t)T * sizeof(float2)), bC = align256((size_t)nC * sizeof(float2));
-    void *d = nullptr;
-    HIP_TRY(hipMalloc(&d, bS + bA + bT + bC));
-    HIP_TRY(hipMemcpy(d, smat.data(), nS * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy((char *)d + bS, amat.data(), nA * sizeof(float4), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy((char *)d + bS + bA, tors.data(), (size_t)T * sizeof(float2), hipMemcpyHostToDevice));
-    HIP_TRY(hipMemcpy((char *)d + bS + bA + bT, acs.data(), (size_t)nC * sizeof(float2),
-                      hipMemcpyHostToDevice));
+    out->o_smat = 0;
+    out->o_amat = bS;
+    out->o_tors = bS + bA;
+    out->o_acs = bS + bA + bT;
+    out->bytes.assign(bS + bA + bT + bC, 0);
+    std::memcpy(out->bytes.data() + out->o_smat, smat.data(), nS * sizeof(float4));
+    std::memcpy(out->bytes.data() + out->o_amat, amat.data(), nA * sizeof(float4));
+    std::memcpy(out->bytes.data() + out->o_tors, tors.data(), (size_t)T * sizeof(float2));
+    std::memcpy(out->bytes.data() + out->o_acs, acs.data(), (size_t)nC * sizeof(float2));
+}
+
+Tables tables_at(const TableBlob &b, char *d) {
     Tables t;
     t.d = d;
-    t.smat = (const float4 *)d;
-    t.amat = (const float4 *)((char *)d + bS);
-    t.tors = (const float2 *)((char *)d + bS + bA);
-    t.acs = (const float2 *)((char *)d + bS + bA + bT);
+    t.smat = (const float4 *)(d + b.o_smat);
+    t.amat = (const float4 *)(d + b.o_amat);
+    t.tors = (const float2 *)(d + b.o_tors);
+    t.acs = (const float2 *)(d + b.o_acs);
+    return t;
+}
+
+// Device tables of the ordinary entry points: one allocation per distinct
+// (start orientations, R, A, T), kept by the context.
+int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
+    const std::string key = tables_key(p);
+    auto it = c->tables.find(key);
+    if (it != c->tables.end()) {
+        *out = it->second;
+        return DOCK_OK;
+    }
+    TableBlob b;
+    make_tables(p, &b);
+    void *d = nullptr;
+    HIP_TRY(hipMalloc(&d, b.bytes.size()));
+    HIP_TRY(hipMemcpy(d, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice));
+    const Tables t = tables_at(b, (char *)d);
     c->tables[key] = t;
     *out = t;
     return DOCK_OK;
@@ -400,19 +463,54 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
     return DOCK_OK;
 }
 
-// Enqueue the whole pipeline for a device-resident library.
+// Bytes of the scratch array a dock_ligands_batch_noalloc call uses: its tables
+// followed by its workspace.
+size_t noalloc_bytes(const dock_library *lib, const dock_params *p, bool user_trace) {
+    const size_t R = (size_t)p->restarts, A = (size_t)p->align_steps, T = (size_t)p->torsion_steps;
+    const size_t nC = (A + kAlignJ - 1) / kAlignJ * kAlignJ;
+    const size_t tables = align256(R * 3 * sizeof(float4)) + align256(A * A * 3 * sizeof(float4)) +
+                          align256(T * sizeof(float2)) + align256(nC * sizeof(float2));
+    return tables + ws_layout(lib, p, user_trace).total;
+}
+
+// Enqueue the whole pipeline for a device-resident library.  With `scratch`
+// (dock_ligands_batch_noalloc) the tables and the workspace are placed in that
+// buffer, nothing is allocated on the device, no graph is captured and no phase
+// timing is recorded.
 int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
-                  const dock_results *o, hipStream_t s) {
+                  const dock_results *o, hipStream_t s, char *scratch = nullptr) {
     if (lib->n_ligands == 0) return DOCK_OK;
     Tables tb;
-    int rc = get_tables(c, p, &tb);
-    if (rc) return rc;
     const bool user_trace = o->trace != nullptr;
     const WsLayout wl = ws_layout(lib, p, user_trace);
-    void *wb = nullptr;
-    rc = get_workspace(c, s, wl.total, &wb);
-    if (rc) return rc;
-    char *base = (char *)wb;
+    char *base = nullptr;
+    if (scratch) {
+        const size_t need = noalloc_bytes(lib, p, user_trace);
+        if (need > (size_t)DOCK_NOALLOC_SCRATCH_BYTES)
+            return fail(DOCK_EINVAL, "request needs " + std::to_string(need) +
+                                         " B of scratch memory, more than the " +
+                                         std::to_string((size_t)DOCK_NOALLOC_SCRATCH_BYTES) +
+                                         " B of DOCK_NOALLOC_SCRATCH_BYTES");
+        const std::string key = tables_key(p);
+        auto it = c->noalloc_tables.find(key);
+        if (it == c->noalloc_tables.end()) {
+            TableBlob b;
+            make_tables(p, &b);
+            it = c->noalloc_tables.emplace(key, std::move(b)).first;
+        }
+        const TableBlob &b = it->second;
+        HIP_TRY(hipMemcpyAsync(scratch, b.bytes.data(), b.bytes.size(), hipMemcpyHostToDevice, s));
+        tb = tables_at(b, scratch);
+        base = scratch + align256(b.bytes.size());
+    } else {
+        int rc = get_tables(c, p, &tb);
+        if (rc) return rc;
+        void *wb = nullptr;
+        rc = get_workspace(c, s, wl.total, &wb);
+        if (rc) return rc;
+        base = (char *)wb;
+    }
+    const bool timed = c->timing && !scratch;
 
     GridArgs g = pk.g;
     SearchArgs sa{};
@@ -456,7 +554,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     wa.rscore = (float *)(base + wl.rscore);
     wa.rtrace = user_trace ? o->trace : (uint16_t *)(base + wl.rtrace);
     wa.acc_pose = (float *)(base + wl.acc);
-    wa.scored = c->timing ? c->d_scored : nullptr;
+    wa.scored = timed ? c->d_scored : nullptr;
 
     OutArgs oa{};
     oa.best = o->best_score;
@@ -469,7 +567,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     oa.ftrace = o->final_trace;
 
     std::array<hipEvent_t, 5> ev{};
-    if (c->timing) {
+    if (timed) {
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         c->marks.push_back(ev);
     }
@@ -507,7 +605,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         if (marks) HIP_TRY(hipEventRecord(ev[4], s));
         return DOCK_OK;
     };
-    if (c->timing || s == nullptr) return sequence(c->timing);
+    if (timed || s == nullptr || scratch) return sequence(timed);
     // graph key: everything the kernels' arguments depend on
     std::string key((const char *)&g, sizeof(g));
     key.append((const char *)&sa, sizeof(sa));
@@ -616,6 +714,13 @@ int dock_create(int device, uint64_t hbm_budget_bytes, dock_ctx **out) {
     c->num_cu = prop.multiProcessorCount;
     c->budget = (size_t)hbm_budget_bytes;
     c->lds_arena = (int)std::min<size_t>(prop.sharedMemPerBlock, (size_t)160 * 1024);
+    {
+        const int rc = scratch_address(device, &c->scratch);
+        if (rc) {
+            delete c;
+            return rc;
+        }
+    }
     for (int i = 0; i < kSubmitStreams; ++i) {
         hipStream_t t = nullptr;
         if (hipStreamCreateWithFlags(&t, hipStreamNonBlocking) != hipSuccess) {
@@ -750,6 +855,24 @@ int dock_ligands_batch(dock_ctx *c, int32_t pocket, const dock_library *lib,
     if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
     HIP_TRY(hipSetDevice(c->device));
     return enqueue_batch(c, it->second, lib, p, o, (hipStream_t)stream);
+}
+
+int dock_ligands_batch_noalloc(dock_ctx *c, int32_t pocket, const dock_library *lib,
+                               const dock_params *p, dock_results *o, void *stream) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->mode != DOCK_MODE_BATCHED)
+        return fail(DOCK_EINVAL, "dock_ligands_batch_noalloc runs the batched form only");
+    rc = check_library_shape(lib);
+    if (rc) return rc;
+    rc = check_results(o, lib->n_ligands);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    HIP_TRY(hipSetDevice(c->device));
+    return enqueue_batch(c, it->second, lib, p, o, (hipStream_t)stream, c->scratch);
 }
 
 int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock_params *p,

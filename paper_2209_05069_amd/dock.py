@@ -65,7 +65,7 @@ class Timing(ctypes.Structure):
 
 
 EXPORTS = ["dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
-           "dock_ligands_batch", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
+           "dock_ligands_batch", "dock_ligands_batch_noalloc", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
            "dock_request_bytes", "dock_set_timing", "dock_submit", "dock_wait"]
 
 _lib = None
@@ -88,6 +88,9 @@ def lib():
         L.dock_pocket_unload.argtypes = [P, ctypes.c_int32]
         L.dock_ligands_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
                                          ctypes.POINTER(Params), ctypes.POINTER(Results), P]
+        L.dock_ligands_batch_noalloc.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
+                                                 ctypes.POINTER(Params), ctypes.POINTER(Results),
+                                                 P]
         L.dock_submit.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
                                   ctypes.POINTER(Params), ctypes.POINTER(Results),
                                   ctypes.POINTER(ctypes.c_uint64)]
@@ -292,6 +295,23 @@ def dock_ligands_batch(ctx, pocket: int, dlib: DeviceLibrary, params: SearchPara
         stream = stream.cuda_stream
     _check(lib().dock_ligands_batch(ctx, pocket, ctypes.byref(dlib.s), ctypes.byref(params.s),
                                     ctypes.byref(res.s), ctypes.c_void_p(stream)))
+
+
+NOALLOC_SCRATCH_BYTES = 64 << 20  # DOCK_NOALLOC_SCRATCH_BYTES
+
+
+def dock_ligands_batch_noalloc(ctx, pocket: int, dlib: DeviceLibrary, params: SearchParams,
+                               res: DeviceResults, stream=None):
+    """dock_ligands_batch that allocates no device memory (tables and workspace in
+    the library's fixed scratch array; batched form only, see include/dock.h)."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    _check(lib().dock_ligands_batch_noalloc(ctx, pocket, ctypes.byref(dlib.s),
+                                            ctypes.byref(params.s), ctypes.byref(res.s),
+                                            ctypes.c_void_p(stream)))
 
 
 class Submission:
