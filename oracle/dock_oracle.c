@@ -33,6 +33,12 @@
  * exhaustive torsion search on 1-2 bond ligands, geometric invariants,
  * hand-made selection cases); see tests/test_oracle_pins.py.
  *
+ * Pairwise rescoring stand-in (oracle_contacts): the paper's Rescore Pose
+ * compares every ligand atom with every pocket atom and accumulates the pair
+ * terms per pose; its chemical terms are not given, so the stand-in pair term is
+ * an integer weight per (ligand type, pocket atom type) for pairs closer than a
+ * contact distance.
+ *
  * Follow mode: given another implementation's decisions (alignment index and
  * torsion step per decision, kept restarts and final alignment index), the
  * oracle recomputes every candidate in FP64, checks that the given choice is
@@ -557,4 +563,30 @@ int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
     free(ord); free(fidx); free(fscore); free(fpose); free(sel);
     free(Y); free(scores); free(poses); free(X); free(C.topo);
     return 0;
+}
+
+/* ------------------------------------------------------------------------- */
+/* Contact score of a pose (stand-in for the chemical Rescore Pose): the sum,
+ * over every ligand atom i and every pocket atom j, of weight[type_i][type_j]
+ * for the pairs with |x_i - p_j| < contact_dist.  All l x p pairs are visited,
+ * as the paper's rescoring does.  *boundary (when not NULL) receives the sum of
+ * |weight| over the pairs whose distance lies within tol of contact_dist: the
+ * pairs whose verdict a rounding of the positions by up to tol could change. */
+long long oracle_contacts(const or_pocket_atoms *pa, int n, const uint8_t *type,
+                          const double *xyz, double tol, long long *boundary) {
+    const double dc = pa->contact_dist;
+    long long sum = 0, edge = 0;
+    for (int i = 0; i < n; ++i) {
+        for (int j = 0; j < pa->n_atoms; ++j) {
+            const double dx = xyz[3 * i + 0] - (double)pa->xyz[3 * j + 0];
+            const double dy = xyz[3 * i + 1] - (double)pa->xyz[3 * j + 1];
+            const double dz = xyz[3 * i + 2] - (double)pa->xyz[3 * j + 2];
+            const double d = sqrt(dx * dx + dy * dy + dz * dz);
+            const int32_t w = pa->weight[(size_t)type[i] * pa->ntypes + pa->type[j]];
+            if (d < dc) sum += w;
+            if (fabs(d - dc) <= tol) edge += w < 0 ? -(long long)w : (long long)w;
+        }
+    }
+    if (boundary) *boundary = edge;
+    return sum;
 }

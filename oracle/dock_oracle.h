@@ -64,6 +64,17 @@ typedef struct {
     double stats[8];
 } or_result;
 
+/* Pocket atoms of the pairwise rescoring stand-in (Rescore Pose). */
+typedef struct {
+    int n_atoms;
+    int ntypes;                /* pocket atom types */
+    const float *xyz;          /* [n_atoms][3], pocket frame (the grid's), Angstrom */
+    const uint8_t *type;       /* [n_atoms] */
+    double contact_dist;       /* Angstrom */
+    int lig_ntypes;            /* ligand atom types (the grid's types) */
+    const int32_t *weight;     /* [lig_ntypes][ntypes] */
+} or_pocket_atoms;
+
 double oracle_interp(const or_grid *g, int t, const double p[3]);
 double oracle_score(const or_grid *g, int n, const uint8_t *type, const double *xyz);
 int oracle_topo(int n, int nbonds, const int32_t *bonds, int32_t *dist);
@@ -72,6 +83,8 @@ void oracle_quat_matrix(const float q[4], double M[9]);
 void oracle_align_matrix(int A, int o, double M[9]);
 int oracle_select(int R, int n, const double *score, const double *pose, int K, double delta,
                   int32_t *sel);
+long long oracle_contacts(const or_pocket_atoms *pa, int n, const uint8_t *type,
+                          const double *xyz, double tol, long long *boundary);
 int oracle_dock_ligand(const or_grid *g, const or_ligand *L, const or_params *P,
                        const or_follow *F, or_result *out);
 

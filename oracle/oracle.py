@@ -57,6 +57,11 @@ class _Follow(ctypes.Structure):
                 ("tie_rel", ctypes.c_double), ("bump_tol", ctypes.c_double)]
 
 
+class _PocketAtoms(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int), ("ntypes", ctypes.c_int), ("xyz", P), ("type", P),
+                ("contact_dist", ctypes.c_double), ("lig_ntypes", ctypes.c_int), ("weight", P)]
+
+
 class _Result(ctypes.Structure):
     _fields_ = [("restart_score", P), ("restart_pose", P), ("decision_score", P), ("trace", P),
                 ("n_sel", ctypes.c_int32), ("sel_restart", P), ("pose_score", P),
@@ -84,6 +89,9 @@ def _L():
         lib.oracle_align_matrix.argtypes = [ctypes.c_int, ctypes.c_int, P]
         lib.oracle_select.argtypes = [ctypes.c_int, ctypes.c_int, P, P, ctypes.c_int,
                                       ctypes.c_double, P]
+        lib.oracle_contacts.argtypes = [ctypes.POINTER(_PocketAtoms), ctypes.c_int, P, P,
+                                        ctypes.c_double, P]
+        lib.oracle_contacts.restype = ctypes.c_longlong
         lib.oracle_dock_ligand.argtypes = [G, ctypes.POINTER(_Ligand), ctypes.POINTER(_Params),
                                            ctypes.POINTER(_Follow), ctypes.POINTER(_Result)]
         _lib = lib
@@ -155,6 +163,34 @@ def select(scores, poses, K, delta):
     sel = np.zeros(max(K, R), np.int32)
     ns = _L().oracle_select(R, n, _ptr(scores), _ptr(poses), K, float(delta), _ptr(sel))
     return sel[:ns].copy()
+
+
+class PocketAtoms:
+    """Pocket atoms of the pairwise rescoring stand-in (keeps the arrays alive)."""
+
+    def __init__(self, xyz, types, ntypes, weight, contact_dist):
+        self.xyz = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+        self.type = np.ascontiguousarray(types, np.uint8)
+        self.weight = np.ascontiguousarray(weight, np.int32)
+        lig_ntypes, nt = self.weight.shape
+        assert nt == ntypes
+        self.s = _PocketAtoms(len(self.type), int(ntypes), _ptr(self.xyz), _ptr(self.type),
+                              float(contact_dist), int(lig_ntypes), _ptr(self.weight))
+
+    @classmethod
+    def of(cls, pa):
+        return cls(pa.xyz, pa.type, pa.ntypes, pa.weight, pa.contact_dist)
+
+
+def contacts(pocket_atoms, types, xyz, tol=0.0):
+    """(contact score, boundary weight) of a pose: see oracle_contacts."""
+    pa = pocket_atoms if isinstance(pocket_atoms, PocketAtoms) else PocketAtoms.of(pocket_atoms)
+    types = np.ascontiguousarray(types, np.uint8)
+    xyz = np.ascontiguousarray(xyz, np.float64).reshape(-1, 3)
+    b = ctypes.c_longlong(0)
+    v = _L().oracle_contacts(ctypes.byref(pa.s), len(types), _ptr(types), _ptr(xyz), float(tol),
+                             ctypes.byref(b))
+    return int(v), int(b.value)
 
 
 class LigandArrays:

@@ -6,6 +6,8 @@ This module makes inputs only; it contains no docking arithmetic.
 from .synth import (  # noqa: F401
     Library,
     Pocket,
+    PocketAtoms,
+    pocket_atoms,
     build,
     library_uniform,
     library_lognormal,

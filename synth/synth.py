@@ -140,6 +140,43 @@ def pocket_gaussians(seed: int, ntypes: int, n: int, spacing: float, ngauss: int
     return Pocket(values=vals, spacing=float(spacing), origin=(o, o, o), gaussians=g)
 
 
+@dataclass
+class PocketAtoms:
+    """Pocket atoms for the pairwise rescoring stand-in: positions in the grid's
+    frame (float32 [n, 3]), types (uint8 [n]), the integer pair weight of a
+    ligand atom of grid type t and a pocket atom of type u (int32 [t, u]), and
+    the contact distance (Angstrom)."""
+    xyz: np.ndarray
+    type: np.ndarray
+    ntypes: int
+    weight: np.ndarray
+    contact_dist: float
+
+
+def pocket_atoms(seed: int, pocket: Pocket, density: float = 0.04, cavity_frac: float = 0.4,
+                 ntypes: int = 4, contact_dist: float = 4.0, weights=(-2, 3)) -> PocketAtoms:
+    """Atoms uniform in the grid box (density per cubic Angstrom) outside a central
+    cavity sphere (radius cavity_frac times the half extent), where the docked
+    ligands sit; types U{0..ntypes-1}; weights U{weights[0]..weights[1]}."""
+    rng = np.random.default_rng([seed, 0x6A70])
+    nx, ny, nz = pocket.shape_xyz
+    half = pocket.spacing * (np.array([nx, ny, nz]) - 1) / 2.0
+    centre = np.array(pocket.origin) + half
+    rc = cavity_frac * float(half.min())
+    vol = float(np.prod(2 * half)) - 4.0 / 3.0 * np.pi * rc ** 3
+    n = int(round(density * vol))
+    pts = np.zeros((0, 3))
+    while len(pts) < n:
+        cand = rng.uniform(-half, half, size=(2 * n + 16, 3))
+        cand = cand[np.linalg.norm(cand, axis=1) >= rc]
+        pts = np.concatenate([pts, cand])
+    xyz = (pts[:n] + centre).astype(np.float32)
+    typ = rng.integers(0, ntypes, size=n).astype(np.uint8)
+    w = rng.integers(weights[0], weights[1] + 1, size=(pocket.ntypes, ntypes)).astype(np.int32)
+    return PocketAtoms(xyz=xyz, type=typ, ntypes=int(ntypes), weight=w,
+                       contact_dist=float(contact_dist))
+
+
 def library_from_sizes(seed: int, n_atoms, n_rot, ntypes: int = 4, clash_dist: float = 2.05,
                        mask_words: int | None = None) -> Library:
     n_atoms = np.ascontiguousarray(n_atoms, np.int32)
