@@ -56,6 +56,10 @@ def parse():
     ap.add_argument("--latency-ligands", type=int, default=32,
                     help="ligands docked one per call in the plain form for its per-ligand "
                          "latency (0: skip)")
+    ap.add_argument("--no-tune", action="store_true",
+                    help="keep the default tiles (no per-bin autotuning before the timed steps)")
+    ap.add_argument("--tune-ligands", type=int, default=4096,
+                    help="ligands of the size-stratified sample the per-bin autotuner times on")
     ap.add_argument("--no-prune", action="store_true",
                     help="the no-early-exit ablation: no bump-check pruning (bump_prune=0)")
     ap.add_argument("--serve", action="store_true",
@@ -364,7 +368,8 @@ def plain_form(D, torch, ctx, pid, lib, q, s, order, n_sample, n_latency, stream
     out = {"ligands_per_s": sub.n_ligands / (pms * 1e-3), "sample_ligands": sub.n_ligands,
            "sample": "size-stratified (heavy-atom quartile x rotatable-bond half), seeded",
            "ms": pms,
-           "form": "one ligand per launch sequence (checks, R restart workgroups, select/final), "
+           "form": "one ligand per launch sequence (checks, R restart workgroups, selection, "
+                   "one workgroup per kept pose for the final alignment, outputs), "
                    "ligands round-robin over 4 streams"}
     if n_latency > 0:
         lat = []
@@ -421,6 +426,18 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    order = stratified_order(lib, 2209)
+    tuning = None
+    if not a.no_tune:
+        t1 = time.time()
+        tsub = lib.subset(sorted(order[:min(a.tune_ligands, lib.n_ligands)]))
+        table = D.dock_autotune(ctx, pid, D.DeviceLibrary(tsub), params, stream)
+        tuning = {"sample_ligands": tsub.n_ligands, "seconds": time.time() - t1,
+                  "sample": "size-stratified (heavy-atom quartile x rotatable-bond half), seeded",
+                  "bins": {f"atoms {32 * b + 1}-{32 * (b + 1)}": t
+                           for b, t in enumerate(table) if t["ligands"] > 0}}
+        print(f"[bench] autotuned in {tuning['seconds']:.1f}s: {tuning['bins']}",
+              file=sys.stderr, flush=True)
     for w in range(a.warmup):
         D.dock_ligands_batch(ctx, pid, dl, params, res, stream)
         torch.cuda.synchronize()
@@ -515,7 +532,7 @@ def main():
             "kernels": kernels,
         },
     }
-    order = stratified_order(lib, 2209)
+    out["tuning"] = tuning if tuning is not None else "default tiles (--no-tune)"
     if a.plain_ligands > 0:
         pf = plain_form(D, torch, ctx, pid, lib, q, dict(s, bump_prune=prune), order,
                         min(a.plain_ligands, L), min(a.latency_ligands, L), stream)

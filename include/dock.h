@@ -215,7 +215,8 @@ int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
  * tables (16*3R B of start rotations, 16*3A^2 B of alignment rotations, 8*T B
  * of torsion (cos, sin), 8*(A rounded up to 32) B of alignment (cos, sin)) plus
  * the workspace (per atom 32 B of bump-pair rows and 12*top_k B of kept poses;
- * per ligand 4*R B of restart scores and 32 B of bin lists; 128 B of counters;
+ * per ligand 4*R B of restart scores, 32 B of bin lists and 12*top_k + 4 B of
+ * selection records; 128 B of counters;
  * and, when out->trace is NULL, 2*R*(L + P*n_rot_total) B of decision trace),
  * each part rounded up to a multiple of 256 B.
  * Every call on a device shares that device's array and leaves its contents
@@ -246,6 +247,39 @@ int dock_request_bytes(const dock_library *lib, const dock_params *params,
 int dock_poll(dock_ctx *ctx, uint64_t ticket, int32_t *done);
 /* Block until `ticket` is done, then retire it. */
 int dock_wait(dock_ctx *ctx, uint64_t ticket);
+
+/* Per-bin autotuning of the batched form's tiles (paper: the batched form sizes
+ * its launches per size bucket from the GPU's occupancy; Batched Implementation
+ * subsection).  Size bin b holds the ligands with 32b < atoms <= 32(b+1).  For
+ * each bin the sample has ligands in, dock_autotune docks the sample once,
+ * then times the torsion-sweep kernel with 2, 4 and 8 restarts (waves) per
+ * workgroup, the pose-selection kernel with 4, 8 and 16 waves per workgroup,
+ * and the final-alignment kernel with 2, 4 and 8 waves per workgroup at 1, 2,
+ * 4 or all workgroups per CU that fit, each the best of two runs on `stream`;
+ * the fastest tile of each kernel is kept by the context for these search
+ * settings (restarts, torsion_steps, align_steps, top_k, sweep_passes) and used
+ * by every later batched call with them (results do not depend on the tiles).
+ * `sample` is device memory, as for dock_ligands_batch; `out` (NULL to skip)
+ * receives DOCK_NUM_BINS entries.  The call allocates its own result buffers,
+ * waits for `stream` and returns when done. */
+#define DOCK_NUM_BINS 8
+typedef struct {
+    int32_t ligands;         /* ligands of the sample in the bin (0: not tuned) */
+    int32_t dock_waves;      /* torsion sweep: restarts (waves) per workgroup */
+    int32_t select_waves;    /* pose selection: waves per workgroup */
+    int32_t falign_waves;    /* final alignment: waves per workgroup */
+    int32_t falign_per_cu;   /* final alignment: workgroups per CU (0: all that fit) */
+    float dock_ms, select_ms, falign_ms;  /* the chosen tiles on the sample */
+    float dock_ms_default, select_ms_default, falign_ms_default;  /* the default tiles
+                                                (4, 4, 4 waves, all that fit) */
+} dock_bin_tuning;
+
+int dock_autotune(dock_ctx *ctx, int32_t pocket, const dock_library *sample,
+                  const dock_params *params, dock_bin_tuning *out, void *stream);
+/* Set the tiles used for these search settings from `table` (DOCK_NUM_BINS
+ * entries; entries with ligands = 0 keep the defaults), e.g. a table saved from
+ * an earlier dock_autotune on the same device; NULL restores the defaults. */
+int dock_set_tuning(dock_ctx *ctx, const dock_params *params, const dock_bin_tuning *table);
 
 /* Phase timing, for measurement.  While enabled, every dock_ligands_batch
  * call records HIP events on its own stream before its prep kernel, after it,

@@ -1633,32 +1633,41 @@ __device__ void replay_pose(Pose<NS> &Y, const float4 *xyzt, const u64 *mask, co
 }
 
 // ---------------------------------------------------------------------------
-// Select Poses + final rigid step + output, one workgroup per ligand (persistent
-// over the bin list).
-// k_final's shared memory: staged ligand, per-wave alignment records, restart
-// keys and order, selection and output scratch, then (sel_lds) the batch of
-// candidate poses and the kept poses.
+// Final stage (Select Poses, then the final rigid step and score of every kept
+// pose, then the outputs), as three kernels per size bin:
+//   k_select: one workgroup per ligand (persistent over the bin list): ranks the
+//     restarts, rebuilds candidates from their traces and keeps them greedily;
+//     writes the kept poses (workspace acc_pose), their restarts and count;
+//   k_falign: one wave per (ligand, kept pose) item (the grid's waves take the
+//     bin's items in turn), or in the plain form one workgroup per kept pose
+//     with the orientations split over its waves: alignment again about the
+//     pose centroid, final score and orientation;
+//   k_out: one workgroup per ligand: output order (final score desc, restart
+//     asc), scores, restarts, final-step indices, and the kept poses turned by
+//     their final-step orientation.
+// k_select's shared memory: staged ligand, restart keys and order, selection
+// scratch, then (sel_lds) the batch of candidate poses and the kept poses.
 
-static __host__ __device__ size_t final_sel_offset(int nmax, int waves, int R, int K) {
+static __host__ __device__ size_t select_sel_offset(int nmax, int waves, int R, int K) {
     const int nw = (nmax + 63) / 64;
-    const size_t b = Lds::rec(nmax, nw) + (size_t)waves * (size_t)nmax * 16 + (size_t)R * 12 +
-                     (size_t)K * 16 + 4 + (size_t)(2 * waves + 1) * 4;
+    const size_t b = Lds::rec(nmax, nw) + (size_t)R * 12 + (size_t)K * 4 + 4 +
+                     (size_t)(2 * waves + 1) * 4;
     return (b + 15) & ~(size_t)15;
 }
 
-size_t final_lds_bytes(int nmax, int waves, int R, int K, int sel_lds) {
-    return final_sel_offset(nmax, waves, R, K) +
+size_t select_lds_bytes(int nmax, int waves, int R, int K, int sel_lds) {
+    return select_sel_offset(nmax, waves, R, K) +
            (sel_lds ? (size_t)(waves + K) * (size_t)nmax * 12 : 0);
 }
 
-int final_sel_lds(int nmax, int waves, int R, int K) {
-    return final_lds_bytes(nmax, waves, R, K, 1) <= (size_t)160 * 1024 ? 1 : 0;
+int select_sel_lds(int nmax, int waves, int R, int K) {
+    return select_lds_bytes(nmax, waves, R, K, 1) <= (size_t)160 * 1024 ? 1 : 0;
 }
 
 template <int NS>
-__global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibArgs lib,
-                                               WorkArgs ws, OutArgs out, int bin, int single,
-                                               int sel_lds) {
+__global__ __launch_bounds__(1024) void k_select(GridArgs g, SearchArgs sa, LibArgs lib,
+                                                WorkArgs ws, OutArgs out, int bin, int single,
+                                                int sel_lds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -1668,20 +1677,14 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
     const int2 *rot = (const int2 *)(smem + Lds::rot(nmax, NS));
     int *misc = (int *)(smem + Lds::misc(nmax, NS));
     unsigned char *p = smem + Lds::rec(nmax, NS);
-    float4 *rec = (float4 *)(p + (size_t)wave * nmax * 16);
-    p += (size_t)W * nmax * 16;
-    u64 *rkey = (u64 *)p;                 // [R]
+    u64 *rkey = (u64 *)p;                     // [R]
     int *order = (int *)(p + (size_t)R * 8);  // [R]
     int *sel = (int *)(p + (size_t)R * 12);   // [K]
-    float *fsc = (float *)(sel + K);          // [K]
-    int *fo = (int *)(fsc + K);               // [K]
-    int *rank = fo + K;                       // [K]
-    int *nsel = rank + K;                     // [1]
+    int *nsel = sel + K;                      // [1]
     int *cflag = nsel + 1;                    // [W] candidate conflicts
     int *kinfo = cflag + W;                   // [1 + W] kept count, slot of each wave's candidate
-    float *candL = (float *)(smem + final_sel_offset(nmax, W, R, K));  // [W][n][3]
-    float *keptL = candL + (size_t)W * nmax * 3;                        // [K][n][3]
-    const Tri tr = make_tri(g);
+    float *candL = (float *)(smem + select_sel_offset(nmax, W, R, K));  // [W][n][3]
+    float *keptL = candL + (size_t)W * nmax * 3;                         // [K][n][3]
 
     if (single >= 0 && out.status[single] != 0) return;
     for (int pass = 0;; ++pass) {
@@ -1717,7 +1720,6 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
         float *accp = ws.acc_pose + (size_t)a0 * K * 3;
         const uint16_t *trl = ws.rtrace + trace_base(lib, sa, l);
         const int D = 1 + sa.P * B;
-        float *kposes = sel_lds ? keptL : accp;  // kept poses [s][i][3]
         if (sel_lds) {
             // Select Poses with every wave: per round, wave w replays the restart
             // ranked t0 + w and tests it against the poses kept so far (lanes over
@@ -1801,6 +1803,8 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
                 __syncthreads();
             }
             if (threadIdx.x == 0) *nsel = ns;
+            // kept poses to the workspace, for k_falign
+            for (int e = threadIdx.x; e < ns * n * 3; e += blockDim.x) accp[e] = keptL[e];
         } else if (wave == 0) {
             // greedy selection with plain-RMSD dedup; poses rebuilt from traces
             int ns = 0;
@@ -1846,49 +1850,129 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
         }
         __syncthreads();
         const int ns = *nsel;
-        int toff[NS];
-        lane_toff(xyzt, n, toff);
-        // final rigid step on each kept pose
-        for (int s = wave; s < ns; s += W) {
-            Pose<NS> Y;
-#pragma unroll
-            for (int q = 0; q < NS; ++q) {
-                const int i = lane + 64 * q;
-                const float *P = kposes + ((size_t)s * n + (i < n ? i : 0)) * 3;
-                Y.x[q] = P[0];
-                Y.y[q] = P[1];
-                Y.z[q] = P[2];
-            }
-            int o = 0;
-            if (sa.final_align) o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, WaveSplit());
-            const float sc = pose_score(Y, n, toff, tr, g);
-            if (lane == 0) {
-                fsc[s] = sc;
-                fo[s] = o;
-            }
-        }
+        for (int s = threadIdx.x; s < ns; s += blockDim.x) ws.sel[(size_t)l * K + s] = sel[s];
+        if (threadIdx.x == 0) ws.nsel[l] = ns;
         __syncthreads();
-        // output order: final score desc, restart asc
+    }
+}
+
+// Final rigid step and score of kept pose s of ligand l (Rescore Pose stand-in):
+// the alignment about the pose centroid (if final_align), then the grid score,
+// written to fscore / fo by the lead wave.  The kept pose itself is left as it
+// is (k_out applies the chosen orientation), so the kernel can be run again on
+// the same inputs.  rec: LDS for >= n float4.
+template <int NS, class Split>
+__device__ void final_item(int l, int s, float4 *rec, const Tri &tr, const GridArgs &g,
+                           const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                           const Split &sp, bool lead_wave) {
+    const int lane = lane_id();
+    const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+    const float *P = ws.acc_pose + ((size_t)a0 * sa.K + (size_t)s * n) * 3;
+    Pose<NS> Y;
+    int toff[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int i = lane + 64 * q;
+        const int ii = i < n ? i : 0;
+        Y.x[q] = P[3 * ii + 0];
+        Y.y[q] = P[3 * ii + 1];
+        Y.z[q] = P[3 * ii + 2];
+        toff[q] = i < n ? (int)((uint32_t)lib.type[a0 + i] * g.type_bytes) : 0;
+    }
+    int o = 0;
+    if (sa.final_align) o = align_pose(Y, n, toff, rec, tr, g, sa, nullptr, sp);
+    const float sc = pose_score(Y, n, toff, tr, g);
+    if (lead_wave && lane == 0) {
+        ws.fscore[(size_t)l * sa.K + s] = sc;
+        ws.fo[(size_t)l * sa.K + s] = o;
+    }
+}
+
+size_t falign_lds_bytes(int nmax, int waves, int single) {
+    return single ? (size_t)nmax * 16 + (size_t)waves * 8 : (size_t)waves * nmax * 16;
+}
+
+template <int NS>
+__global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibArgs lib,
+                                               WorkArgs ws, const int *__restrict__ status,
+                                               int bin, int single) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int nmax = bin_nmax(bin);
+    // every lane is active here, so the wave index is read from the first lane
+    const int W = blockDim.x >> 6, wave = uniform_int((int)(threadIdx.x >> 6));
+    const Tri tr = make_tri(g);
+    if (single >= 0) {
+        // plain form: workgroup s takes kept pose s of the ligand, its waves split
+        // the orientations and agree on the best through LDS
+        const int l = single, s = blockIdx.x;
+        if (status[l] != 0 || s >= ws.nsel[l]) return;
+        float4 *rec = (float4 *)smem;
+        u64 *slots = (u64 *)(smem + (size_t)nmax * 16);
+        final_item<NS>(l, s, rec, tr, g, sa, lib, ws, BlockSplit{wave, W, slots}, wave == 0);
+        return;
+    }
+    // batched form: the waves of the grid take the bin's (ligand, kept pose)
+    // items in turn (item = global wave index + k * waves in the grid).  The
+    // item index is scalar arithmetic only: no lane-dependent branch precedes
+    // the loop test, so every lane of a wave runs the same items.
+    float4 *rec = (float4 *)(smem + (size_t)wave * nmax * 16);
+    const long long total = (long long)ws.counters[bin] * sa.K;
+    const long long nwaves = (long long)gridDim.x * W;
+    for (long long item = (long long)blockIdx.x * W + wave; item < total; item += nwaves) {
+        const int li = (int)(item / sa.K), s = (int)(item - (long long)li * sa.K);
+        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        if (s < ws.nsel[l]) final_item<NS>(l, s, rec, tr, g, sa, lib, ws, WaveSplit(), true);
+    }
+}
+
+// Outputs of a ligand's kept poses, ordered by (final score desc, restart asc):
+// each wave takes kept poses in turn, turns it by its final-step orientation
+// (the same arithmetic as the alignment's own apply step) and writes it to its
+// output slot.
+template <int NS>
+__global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArgs ws,
+                                             OutArgs out, int bin, int single) {
+    __shared__ int rank[kMaxTopK];
+    const int K = sa.K;
+    const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
+    for (int li = blockIdx.x;; li += gridDim.x) {
+        int l;
+        if (single >= 0) {
+            if (li > 0 || out.status[single] != 0) break;
+            l = single;
+        } else {
+            if (li >= ws.counters[bin]) break;
+            l = ws.bin_list[(size_t)bin * lib.L + li];
+        }
+        const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+        const int ns = ws.nsel[l];
+        const float *fsc = ws.fscore + (size_t)l * K;
+        const int *sel = ws.sel + (size_t)l * K;
+        const int *fo = ws.fo + (size_t)l * K;
         for (int s = threadIdx.x; s < ns; s += blockDim.x) {
             const u64 ks = make_key(fsc[s], (uint32_t)sel[s]);
             int rk = 0;
             for (int q = 0; q < ns; ++q) rk += make_key(fsc[q], (uint32_t)sel[q]) > ks;
             rank[s] = rk;
+            out.pscore[(size_t)l * K + rk] = fsc[s];
+            out.prestart[(size_t)l * K + rk] = sel[s];
+            if (out.ftrace) out.ftrace[(size_t)l * K + rk] = (uint16_t)fo[s];
+            if (rk == 0) out.best[l] = fsc[s];
         }
         __syncthreads();
+        const float *acc = ws.acc_pose + (size_t)a0 * K * 3;
         for (int s = wave; s < ns; s += W) {
             Pose<NS> Y;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const int i = lane + 64 * q;
-                const float *P = kposes + ((size_t)s * n + (i < n ? i : 0)) * 3;
+                const float *P = acc + ((size_t)s * n + (i < n ? i : 0)) * 3;
                 Y.x[q] = P[0];
                 Y.y[q] = P[1];
                 Y.z[q] = P[2];
             }
             if (sa.final_align) apply_align(Y, n, fo[s], sa);
-            const int rk = rank[s];
-            float *O = out.pxyz + ((size_t)a0 * K + (size_t)rk * n) * 3;
+            float *O = out.pxyz + ((size_t)a0 * K + (size_t)rank[s] * n) * 3;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
                 const int i = lane + 64 * q;
@@ -1898,14 +1982,9 @@ __global__ __launch_bounds__(1024) void k_final(GridArgs g, SearchArgs sa, LibAr
                     O[3 * i + 2] = Y.z[q];
                 }
             }
-            if (lane == 0) {
-                out.pscore[(size_t)l * K + rk] = fsc[s];
-                out.prestart[(size_t)l * K + rk] = sel[s];
-                if (out.ftrace) out.ftrace[(size_t)l * K + rk] = (uint16_t)fo[s];
-                if (rk == 0) out.best[l] = fsc[s];
-            }
         }
-        for (int e = threadIdx.x; e < (K - ns) * n * 3; e += blockDim.x)
+        const int per = 3 * n;
+        for (int e = threadIdx.x; e < (K - ns) * per; e += blockDim.x)
             out.pxyz[((size_t)a0 * K + (size_t)ns * n) * 3 + e] = 0.f;
         for (int s = ns + (int)threadIdx.x; s < K; s += blockDim.x) {
             out.pscore[(size_t)l * K + s] = -INFINITY;
@@ -2061,8 +2140,10 @@ __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs 
     if (lane == 0) out.status[l] = status;
 }
 
-__global__ void k_reset(int *counters) {
-    if (threadIdx.x < kNumCounters) counters[threadIdx.x] = 0;
+// Zero counters [first, first + count) (count <= 64): work-queue counters are
+// cleared by a kernel, not a memset, so the sequence can be captured in a graph.
+__global__ void k_reset(int *counters, int first, int count) {
+    if ((int)threadIdx.x < count) counters[first + threadIdx.x] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2090,8 +2171,10 @@ hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blo
     return hipGetLastError();
 }
 
-hipError_t launch_reset(int *counters, hipStream_t s) {
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters);
+hipError_t launch_reset(int *counters, int first, int count, hipStream_t s) {
+    if (first < 0 || count < 0 || count > 64 || first + count > kNumCounters)
+        return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters, first, count);
     return hipGetLastError();
 }
 
@@ -2177,27 +2260,61 @@ hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const 
 }
 
 template <int NS>
-static hipError_t launch_final_t(int bin, int blocks, int waves, const GridArgs &g,
-                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
-                                 const OutArgs &out, int single, hipStream_t s) {
-    const int sel = final_sel_lds(bin_nmax(bin), waves, sa.R, sa.K);
-    const size_t lds = final_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K, sel);
-    hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+static hipError_t launch_select_t(int bin, int blocks, int waves, const GridArgs &g,
+                                  const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                  const OutArgs &out, int single, hipStream_t s) {
+    const int sel = select_sel_lds(bin_nmax(bin), waves, sa.R, sa.K);
+    const size_t lds = select_lds_bytes(bin_nmax(bin), waves, sa.R, sa.K, sel);
+    hipFuncSetAttribute((const void *)k_select<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-    hipLaunchKernelGGL((k_final<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
+    hipLaunchKernelGGL((k_select<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
                        bin, single, sel);
     return hipGetLastError();
 }
 
-hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                        hipStream_t s) {
+hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
+                         hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_final_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 2: return launch_final_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 3: return launch_final_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        default: return launch_final_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 1: return launch_select_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 2: return launch_select_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 3: return launch_select_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        default: return launch_select_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
     }
+}
+
+template <int NS>
+static hipError_t launch_falign_t(int bin, int blocks, int waves, const GridArgs &g,
+                                  const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                                  const OutArgs &out, int single, hipStream_t s) {
+    const size_t lds = falign_lds_bytes(bin_nmax(bin), waves, single >= 0 ? 1 : 0);
+    hipFuncSetAttribute((const void *)k_falign<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    hipLaunchKernelGGL((k_falign<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws,
+                       (const int *)out.status, bin, single);
+    return hipGetLastError();
+}
+
+hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
+                         hipStream_t s) {
+    switch (bin_slots(bin)) {
+        case 1: return launch_falign_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 2: return launch_falign_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 3: return launch_falign_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        default: return launch_falign_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+    }
+}
+
+hipError_t launch_out(int bin, int blocks, const SearchArgs &sa, const LibArgs &lib,
+                      const WorkArgs &ws, const OutArgs &out, int single, hipStream_t s) {
+    switch (bin_slots(bin)) {
+        case 1: hipLaunchKernelGGL(k_out<1>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
+        case 2: hipLaunchKernelGGL(k_out<2>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
+        case 3: hipLaunchKernelGGL(k_out<3>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
+        default: hipLaunchKernelGGL(k_out<4>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
+    }
+    return hipGetLastError();
 }
 
 // k_align geometry: JM = kAlignJ y rotations per lane, the y range in
@@ -2299,24 +2416,45 @@ int dock_blocks_per_cu(int bin, int waves, int T) {
 }
 
 template <int NS>
-static int final_occ(int bin, int waves, int R, int K) {
+static int select_occ(int bin, int waves, int R, int K) {
     int nb = 0;
-    const size_t lds =
-        final_lds_bytes(bin_nmax(bin), waves, R, K, final_sel_lds(bin_nmax(bin), waves, R, K));
-    hipFuncSetAttribute((const void *)k_final<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+    const size_t lds = select_lds_bytes(bin_nmax(bin), waves, R, K,
+                                        select_sel_lds(bin_nmax(bin), waves, R, K));
+    hipFuncSetAttribute((const void *)k_select<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_final<NS>, 64 * waves, lds) !=
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_select<NS>, 64 * waves, lds) !=
         hipSuccess)
         return 1;
     return nb > 0 ? nb : 1;
 }
 
-int final_blocks_per_cu(int bin, int waves, int R, int K) {
+int select_blocks_per_cu(int bin, int waves, int R, int K) {
     switch (bin_slots(bin)) {
-        case 1: return final_occ<1>(bin, waves, R, K);
-        case 2: return final_occ<2>(bin, waves, R, K);
-        case 3: return final_occ<3>(bin, waves, R, K);
-        default: return final_occ<4>(bin, waves, R, K);
+        case 1: return select_occ<1>(bin, waves, R, K);
+        case 2: return select_occ<2>(bin, waves, R, K);
+        case 3: return select_occ<3>(bin, waves, R, K);
+        default: return select_occ<4>(bin, waves, R, K);
+    }
+}
+
+template <int NS>
+static int falign_occ(int bin, int waves) {
+    int nb = 0;
+    const size_t lds = falign_lds_bytes(bin_nmax(bin), waves, 0);
+    hipFuncSetAttribute((const void *)k_falign<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
+                        (int)lds);
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&nb, k_falign<NS>, 64 * waves, lds) !=
+        hipSuccess)
+        return 1;
+    return nb > 0 ? nb : 1;
+}
+
+int falign_blocks_per_cu(int bin, int waves) {
+    switch (bin_slots(bin)) {
+        case 1: return falign_occ<1>(bin, waves);
+        case 2: return falign_occ<2>(bin, waves);
+        case 3: return falign_occ<3>(bin, waves);
+        default: return falign_occ<4>(bin, waves);
     }
 }
 

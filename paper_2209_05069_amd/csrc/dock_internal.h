@@ -12,7 +12,8 @@ constexpr int kMaxTorsionSteps = 1024;  // matches DOCK_MAX_TORSION_STEPS
 constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+1)
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
-constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, final_next, align_next
+constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, select_next, align_next
+constexpr int kMaxTopK = 64;        // matches DOCK_MAX_TOP_K
 constexpr int kAlignJ = 32;         // k_align: y rotations per lane
 constexpr int kAlignMaxGroup = 64;  // k_align: restarts per item at most
 
@@ -69,11 +70,15 @@ struct LibArgs {
 
 struct WorkArgs {
     unsigned long long *far;  // [A_total][kFarWords]
-    int *counters;            // [kNumCounters]: bin_count, dock_next, final_next, align_next
+    int *counters;            // [kNumCounters]: bin_count, dock_next, select_next, align_next
     int *bin_list;            // [kNumBins][L]
     float *rscore;            // [L][R]
     uint16_t *rtrace;         // [R*(L + P*Nr_total)]
-    float *acc_pose;          // [A_total*K*3] kept poses before the final step
+    float *acc_pose;          // [A_total*K*3] kept poses (aligned by the final step in place)
+    int *sel;                 // [L*K] restart of each kept pose
+    int *nsel;                // [L] kept poses
+    float *fscore;            // [L*K] final score of each kept pose
+    int *fo;                  // [L*K] final-step orientation of each kept pose
     unsigned long long *scored;  // torsion samples scored (measurement; null: not counted)
 };
 
@@ -91,14 +96,16 @@ struct OutArgs {
 // Shared-memory bytes of the docking kernel for a bin with at most nmax atoms
 // and `waves` wavefronts per workgroup.
 size_t dock_lds_bytes(int nmax, int waves);
-size_t final_lds_bytes(int nmax, int waves, int R, int K, int sel_lds);
-// Whether k_final keeps candidate and kept poses in LDS (parallel selection).
-int final_sel_lds(int nmax, int waves, int R, int K);
+size_t select_lds_bytes(int nmax, int waves, int R, int K, int sel_lds);
+// Whether k_select keeps candidate and kept poses in LDS (parallel selection).
+int select_sel_lds(int nmax, int waves, int R, int K);
+size_t falign_lds_bytes(int nmax, int waves, int single);
 
 // Launchers (return hipError_t of the launch).
 hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, int nx, int ny,
                               int nz, hipStream_t s);
-hipError_t launch_reset(int *counters, hipStream_t s);
+// Zero work-queue counters [first, first + count), count <= 64.
+hipError_t launch_reset(int *counters, int first, int count, hipStream_t s);
 hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
                        const WorkArgs &ws, const OutArgs &out, hipStream_t s);
 hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
@@ -120,10 +127,16 @@ hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
 // Smallest arena k_align accepts for the bin (fixed part plus a minimal region).
 size_t align_lds_min(int bin, int A, int R);
 int align_blocks_per_cu(int bin, int R, int A, int arena);
-// single >= 0: only that ligand (plain form), else the bin's queue.
-hipError_t launch_final(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                        const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                        hipStream_t s);
+// Final stage of a bin.  single >= 0: only that ligand (plain form; k_falign then
+// runs one workgroup per kept pose), else the bin's queue.
+hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
+                         hipStream_t s);
+hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
+                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
+                         hipStream_t s);
+hipError_t launch_out(int bin, int blocks, const SearchArgs &sa, const LibArgs &lib,
+                      const WorkArgs &ws, const OutArgs &out, int single, hipStream_t s);
 // Plain form: checks of ligand l only (no size binning), and its restarts
 // (grid = R workgroups of `waves` waves).
 hipError_t launch_prep_one(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
@@ -134,6 +147,7 @@ hipError_t launch_plain(int l, int bin, int waves, const GridArgs &g, const Sear
 size_t plain_lds_bytes(int nmax, int waves);
 // Max resident workgroups per CU for a launch shape (occupancy API).
 int dock_blocks_per_cu(int bin, int waves, int T);
-int final_blocks_per_cu(int bin, int waves, int R, int K);
+int select_blocks_per_cu(int bin, int waves, int R, int K);
+int falign_blocks_per_cu(int bin, int waves);
 
 }  // namespace dockgpu

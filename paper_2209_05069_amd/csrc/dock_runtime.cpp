@@ -102,6 +102,14 @@ struct Tables {
     const float2 *acs = nullptr;
 };
 
+// Tile choice of one size bin for the batched kernels (per-bin autotuner).
+struct BinShape {
+    int dock_waves = 4;     // k_dock: waves (restarts of one ligand) per workgroup
+    int select_waves = 4;   // k_select: waves per workgroup
+    int falign_waves = 4;   // k_falign: waves per workgroup
+    int falign_per_cu = 0;  // k_falign: workgroups per CU (0: as many as fit)
+};
+
 // Host image of a Tables allocation (offsets relative to its start).
 struct TableBlob {
     std::vector<char> bytes;
@@ -140,6 +148,8 @@ struct dock_ctx {
     std::map<std::string, TableBlob> noalloc_tables;
     char *scratch = nullptr;  // this device's copy of the scratch array
     std::map<std::string, int> occ;
+    // per-bin tile choices of dock_autotune, by (R, T, A, K, P)
+    std::map<std::string, std::array<BinShape, kNumBins>> tuned;
     std::vector<hipStream_t> submit_streams;  // dock_submit: requests round-robin over these
     size_t next_submit = 0;
     std::map<uint64_t, Ticket> tickets;
@@ -311,7 +321,7 @@ int get_tables(dock_ctx *c, const dock_params *p, Tables *out) {
 }
 
 struct WsLayout {
-    size_t far, counters, bin_list, rscore, rtrace, acc, total;
+    size_t far, counters, bin_list, rscore, rtrace, acc, sel, nsel, fscore, fo, total;
 };
 
 WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trace) {
@@ -325,6 +335,10 @@ WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trac
     w.rtrace = o;
     if (!user_trace) o += align256(R * (L + (size_t)p->sweep_passes * lib->n_rot_total) * sizeof(uint16_t));
     w.acc = o; o += align256((size_t)lib->n_atoms_total * K * 3 * sizeof(float));
+    w.sel = o; o += align256(L * K * sizeof(int));
+    w.nsel = o; o += align256(L * sizeof(int));
+    w.fscore = o; o += align256(L * K * sizeof(float));
+    w.fo = o; o += align256(L * K * sizeof(int));
     w.total = o;
     return w;
 }
@@ -408,11 +422,11 @@ int occupancy(dock_ctx *c, const std::string &key, int v) {
     return v;
 }
 
-constexpr int kDockWaves = 4;
-constexpr int kFinalWaves = 4;
+constexpr int kOutBlocksPerCu = 4;
 
 constexpr int kPlainWaves = 4;
-constexpr int kPlainFinalWaves = 16;  // plain form: kept poses of one ligand spread over 16 waves
+constexpr int kPlainSelectWaves = 16;  // plain form: a ligand's candidates over 16 waves
+constexpr int kPlainFalignWaves = 4;   // plain form: a workgroup of 4 waves per kept pose
 constexpr int kSubmitStreams = 4;
 constexpr int kPlainStreams = 4;
 
@@ -451,7 +465,9 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
         if (n < 1 || n > kMaxAtoms) continue;  // flagged by the checks
         const int bin = (n - 1) >> 5;
         HIP_TRY(launch_plain(l, bin, kPlainWaves, g, sa, la, wa, oa, t));
-        HIP_TRY(launch_final(bin, 1, kPlainFinalWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_select(bin, 1, kPlainSelectWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_falign(bin, sa.K, kPlainFalignWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_out(bin, 1, sa, la, wa, oa, l, t));
     }
     for (size_t i = 0; i < c->plain_streams.size(); ++i) {
         HIP_TRY(hipEventRecord(c->plain_events[i], c->plain_streams[i]));
@@ -473,13 +489,20 @@ size_t noalloc_bytes(const dock_library *lib, const dock_params *p, bool user_tr
     return tables + ws_layout(lib, p, user_trace).total;
 }
 
-// Enqueue the whole pipeline for a device-resident library.  With `scratch`
-// (dock_ligands_batch_noalloc) the tables and the workspace are placed in that
-// buffer, nothing is allocated on the device, no graph is captured and no phase
-// timing is recorded.
-int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
-                  const dock_results *o, hipStream_t s, char *scratch = nullptr) {
-    if (lib->n_ligands == 0) return DOCK_OK;
+// Kernel arguments of one call.
+struct Launch {
+    GridArgs g;
+    SearchArgs sa;
+    LibArgs la;
+    WorkArgs wa;
+    OutArgs oa;
+};
+
+// Tables, workspace and kernel arguments of a call on a device-resident library
+// and results.  With `scratch` (dock_ligands_batch_noalloc) the tables and the
+// workspace are placed in that buffer and nothing is allocated on the device.
+int prepare_launch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
+                   const dock_results *o, hipStream_t s, char *scratch, bool timed, Launch *L) {
     Tables tb;
     const bool user_trace = o->trace != nullptr;
     const WsLayout wl = ws_layout(lib, p, user_trace);
@@ -510,10 +533,10 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         if (rc) return rc;
         base = (char *)wb;
     }
-    const bool timed = c->timing && !scratch;
-
-    GridArgs g = pk.g;
-    SearchArgs sa{};
+    // zeroed first: the graph key is the bytes of *L, padding included
+    std::memset((void *)L, 0, sizeof(*L));
+    std::memcpy((void *)&L->g, (const void *)&pk.g, sizeof(GridArgs));
+    SearchArgs &sa = L->sa;
     sa.R = p->restarts;
     sa.T = p->torsion_steps;
     sa.P = p->sweep_passes;
@@ -523,7 +546,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     sa.bmin = p->bump_min_bonds;
     sa.prune = p->bump_prune;
     {
-        const double bg = (double)p->bump_dist * (double)g.inv_h;
+        const double bg = (double)p->bump_dist * (double)L->g.inv_h;
         sa.bump2g = (float)(bg * bg);
         sa.dedup2 = (float)((double)p->dedup_rmsd * (double)p->dedup_rmsd);
     }
@@ -532,7 +555,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     sa.tors = tb.tors;
     sa.acs = tb.acs;
 
-    LibArgs la{};
+    LibArgs &la = L->la;
     la.L = lib->n_ligands;
     la.mask_words = lib->mask_words;
     la.A_total = lib->n_atoms_total;
@@ -547,16 +570,20 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     la.rot_bond = lib->rot_bond;
     la.rot_mask = (const unsigned long long *)lib->rot_mask;
 
-    WorkArgs wa{};
+    WorkArgs &wa = L->wa;
     wa.far = (unsigned long long *)(base + wl.far);
     wa.counters = (int *)(base + wl.counters);
     wa.bin_list = (int *)(base + wl.bin_list);
     wa.rscore = (float *)(base + wl.rscore);
     wa.rtrace = user_trace ? o->trace : (uint16_t *)(base + wl.rtrace);
     wa.acc_pose = (float *)(base + wl.acc);
+    wa.sel = (int *)(base + wl.sel);
+    wa.nsel = (int *)(base + wl.nsel);
+    wa.fscore = (float *)(base + wl.fscore);
+    wa.fo = (int *)(base + wl.fo);
     wa.scored = timed ? c->d_scored : nullptr;
 
-    OutArgs oa{};
+    OutArgs &oa = L->oa;
     oa.best = o->best_score;
     oa.npose = o->n_poses;
     oa.status = o->status;
@@ -565,59 +592,121 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
     oa.pxyz = o->pose_xyz;
     oa.rscore_user = o->restart_score;
     oa.ftrace = o->final_trace;
+    return DOCK_OK;
+}
 
+// Launch shapes of the batched sequence, per size bin: workgroup counts from the
+// occupancy API and the bin's tile choice (tuned, or the defaults).
+struct Shapes {
+    BinShape tile[kNumBins];
+    int align_blocks[kNumBins], dock_blocks[kNumBins], select_blocks[kNumBins],
+        falign_blocks[kNumBins];
+    int out_blocks;
+};
+
+std::string tune_key(const SearchArgs &sa) {
+    return std::to_string(sa.R) + "/" + std::to_string(sa.T) + "/" + std::to_string(sa.A) + "/" +
+           std::to_string(sa.K) + "/" + std::to_string(sa.P);
+}
+
+int make_shapes(dock_ctx *c, const Launch &L, const BinShape *tile, Shapes *sh) {
+    const SearchArgs &sa = L.sa;
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        const BinShape &t = tile[bin];
+        sh->tile[bin] = t;
+        if ((size_t)c->lds_arena < align_lds_min(bin, sa.A, sa.R))
+            return fail(DOCK_EDEVICE, "device LDS per workgroup too small for the alignment kernel");
+        const std::string a = "a" + std::to_string(bin) + "/" + std::to_string(sa.R) + "/" +
+                              std::to_string(sa.A) + "/" + std::to_string(c->lds_arena);
+        sh->align_blocks[bin] =
+            occupancy(c, a, align_blocks_per_cu(bin, sa.R, sa.A, c->lds_arena)) * c->num_cu;
+        const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(t.dock_waves) + "/" +
+                              std::to_string((sa.T + 63) / 64);
+        sh->dock_blocks[bin] =
+            occupancy(c, k, dock_blocks_per_cu(bin, t.dock_waves, sa.T)) * c->num_cu;
+        const std::string f = "s" + std::to_string(bin) + "/" + std::to_string(t.select_waves) +
+                              "/" + std::to_string(sa.R) + "/" + std::to_string(sa.K);
+        const int sb =
+            occupancy(c, f, select_blocks_per_cu(bin, t.select_waves, sa.R, sa.K)) * c->num_cu;
+        sh->select_blocks[bin] = sb > L.la.L ? L.la.L : sb;
+        const std::string fa = "fa" + std::to_string(bin) + "/" + std::to_string(t.falign_waves);
+        int per_cu = occupancy(c, fa, falign_blocks_per_cu(bin, t.falign_waves));
+        if (t.falign_per_cu > 0 && t.falign_per_cu < per_cu) per_cu = t.falign_per_cu;
+        sh->falign_blocks[bin] = per_cu * c->num_cu;
+    }
+    sh->out_blocks = std::min(L.la.L, kOutBlocksPerCu * c->num_cu);
+    return DOCK_OK;
+}
+
+// The batched launch sequence: reset, prep, then per stage its launch per bin.
+// marks (optional): events recorded at the phase boundaries.
+int run_sequence(dock_ctx *c, const Launch &L, const Shapes &sh, hipStream_t s,
+                 const std::array<hipEvent_t, 5> *marks) {
+    const GridArgs &g = L.g;
+    const SearchArgs &sa = L.sa;
+    const LibArgs &la = L.la;
+    const WorkArgs &wa = L.wa;
+    const OutArgs &oa = L.oa;
+    HIP_TRY(launch_reset(wa.counters, 0, kNumCounters, s));
+    if (marks) HIP_TRY(hipEventRecord((*marks)[0], s));
+    HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
+    if (marks) HIP_TRY(hipEventRecord((*marks)[1], s));
+    for (int bin = 0; bin < kNumBins; ++bin)
+        HIP_TRY(launch_align(bin, sh.align_blocks[bin], c->lds_arena, g, sa, la, wa, s));
+    if (marks) HIP_TRY(hipEventRecord((*marks)[2], s));
+    for (int bin = 0; bin < kNumBins; ++bin)
+        HIP_TRY(launch_dock(bin, sh.dock_blocks[bin], sh.tile[bin].dock_waves, g, sa, la, wa, s));
+    if (marks) HIP_TRY(hipEventRecord((*marks)[3], s));
+    for (int bin = 0; bin < kNumBins; ++bin)
+        HIP_TRY(launch_select(bin, sh.select_blocks[bin], sh.tile[bin].select_waves, g, sa, la, wa,
+                              oa, -1, s));
+    for (int bin = 0; bin < kNumBins; ++bin)
+        HIP_TRY(launch_falign(bin, sh.falign_blocks[bin], sh.tile[bin].falign_waves, g, sa, la, wa,
+                              oa, -1, s));
+    for (int bin = 0; bin < kNumBins; ++bin)
+        HIP_TRY(launch_out(bin, sh.out_blocks, sa, la, wa, oa, -1, s));
+    if (marks) HIP_TRY(hipEventRecord((*marks)[4], s));
+    return DOCK_OK;
+}
+
+// The tile choice for these search settings: the autotuner's, else the defaults.
+const BinShape *bin_tiles(dock_ctx *c, const SearchArgs &sa) {
+    static const BinShape defaults[kNumBins] = {};
+    auto it = c->tuned.find(tune_key(sa));
+    return it != c->tuned.end() ? it->second.data() : defaults;
+}
+
+// Enqueue the whole pipeline for a device-resident library.  With `scratch`
+// (dock_ligands_batch_noalloc) the tables and the workspace are placed in that
+// buffer, nothing is allocated on the device, no graph is captured and no phase
+// timing is recorded.
+int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
+                  const dock_results *o, hipStream_t s, char *scratch = nullptr) {
+    if (lib->n_ligands == 0) return DOCK_OK;
+    const bool timed = c->timing && !scratch;
+    Launch L;
+    int rc = prepare_launch(c, pk, lib, p, o, s, scratch, timed, &L);
+    if (rc) return rc;
     std::array<hipEvent_t, 5> ev{};
     if (timed) {
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         c->marks.push_back(ev);
     }
-    if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, g, sa, la, wa, oa, ev, s);
+    if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, L.g, L.sa, L.la, L.wa, L.oa, ev, s);
     // launch shapes (occupancy queries stay outside any graph capture)
-    int dock_blocks[kNumBins], final_blocks[kNumBins], align_blocks[kNumBins];
-    for (int bin = 0; bin < kNumBins; ++bin) {
-        if ((size_t)c->lds_arena < align_lds_min(bin, sa.A, sa.R))
-            return fail(DOCK_EDEVICE, "device LDS per workgroup too small for the alignment kernel");
-        const std::string a = "a" + std::to_string(bin) + "/" + std::to_string(sa.R) + "/" +
-                              std::to_string(sa.A) + "/" + std::to_string(c->lds_arena);
-        align_blocks[bin] =
-            occupancy(c, a, align_blocks_per_cu(bin, sa.R, sa.A, c->lds_arena)) * c->num_cu;
-        const std::string k = "d" + std::to_string(bin) + "/" + std::to_string(kDockWaves) + "/" +
-                              std::to_string((sa.T + 63) / 64);
-        dock_blocks[bin] = occupancy(c, k, dock_blocks_per_cu(bin, kDockWaves, sa.T)) * c->num_cu;
-        const std::string f = "f" + std::to_string(bin) + "/" + std::to_string(kFinalWaves) + "/" +
-                              std::to_string(sa.R) + "/" + std::to_string(sa.K);
-        int blocks = occupancy(c, f, final_blocks_per_cu(bin, kFinalWaves, sa.R, sa.K)) * c->num_cu;
-        final_blocks[bin] = blocks > la.L ? la.L : blocks;
-    }
-    auto sequence = [&](bool marks) -> int {
-        HIP_TRY(launch_reset(wa.counters, s));
-        if (marks) HIP_TRY(hipEventRecord(ev[0], s));
-        HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
-        if (marks) HIP_TRY(hipEventRecord(ev[1], s));
-        for (int bin = 0; bin < kNumBins; ++bin)
-            HIP_TRY(launch_align(bin, align_blocks[bin], c->lds_arena, g, sa, la, wa, s));
-        if (marks) HIP_TRY(hipEventRecord(ev[2], s));
-        for (int bin = 0; bin < kNumBins; ++bin)
-            HIP_TRY(launch_dock(bin, dock_blocks[bin], kDockWaves, g, sa, la, wa, s));
-        if (marks) HIP_TRY(hipEventRecord(ev[3], s));
-        for (int bin = 0; bin < kNumBins; ++bin)
-            HIP_TRY(launch_final(bin, final_blocks[bin], kFinalWaves, g, sa, la, wa, oa, -1, s));
-        if (marks) HIP_TRY(hipEventRecord(ev[4], s));
-        return DOCK_OK;
-    };
-    if (timed || s == nullptr || scratch) return sequence(timed);
-    // graph key: everything the kernels' arguments depend on
-    std::string key((const char *)&g, sizeof(g));
-    key.append((const char *)&sa, sizeof(sa));
-    key.append((const char *)&la, sizeof(la));
-    key.append((const char *)&wa, sizeof(wa));
-    key.append((const char *)&oa, sizeof(oa));
+    Shapes sh;
+    rc = make_shapes(c, L, bin_tiles(c, L.sa), &sh);
+    if (rc) return rc;
+    if (timed || s == nullptr || scratch) return run_sequence(c, L, sh, s, timed ? &ev : nullptr);
+    // graph key: everything the kernels' arguments and launch shapes depend on
+    std::string key((const char *)&L, sizeof(L));
+    key.append((const char *)&sh, sizeof(sh));
     key.append((const char *)&s, sizeof(s));
     auto gi = c->graphs.find(key);
     if (gi == c->graphs.end()) {
         if (c->seen_keys[key]++ == 0) {
             if (c->seen_keys.size() > 256) c->seen_keys.clear();
-            return sequence(false);  // first time: eager
+            return run_sequence(c, L, sh, s, nullptr);  // first time: eager
         }
         if (c->graphs.size() >= 16) {
             for (auto &kv : c->graphs) (void)hipGraphExecDestroy(kv.second);
@@ -625,7 +714,7 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         }
         hipGraph_t graph = nullptr;
         HIP_TRY(hipStreamBeginCapture(s, hipStreamCaptureModeRelaxed));
-        const int rc2 = sequence(false);
+        const int rc2 = run_sequence(c, L, sh, s, nullptr);
         const hipError_t ec = hipStreamEndCapture(s, &graph);
         if (rc2) {
             if (graph) (void)hipGraphDestroy(graph);
@@ -873,6 +962,188 @@ int dock_ligands_batch_noalloc(dock_ctx *c, int32_t pocket, const dock_library *
     if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
     HIP_TRY(hipSetDevice(c->device));
     return enqueue_batch(c, it->second, lib, p, o, (hipStream_t)stream, c->scratch);
+}
+
+int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock_params *p,
+                  dock_bin_tuning *out, void *stream) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    int rc = check_params(p);
+    if (rc) return rc;
+    if (p->mode != DOCK_MODE_BATCHED) return fail(DOCK_EINVAL, "dock_autotune tunes the batched form");
+    rc = check_library_shape(lib);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    HIP_TRY(hipSetDevice(c->device));
+    hipStream_t s = (hipStream_t)stream;
+    if (out) std::memset(out, 0, sizeof(dock_bin_tuning) * kNumBins);
+    if (lib->n_ligands == 0) return DOCK_OK;
+    // result buffers of the sample (freed at the end)
+    const size_t L = (size_t)lib->n_ligands, K = (size_t)p->top_k, A = (size_t)lib->n_atoms_total;
+    size_t off = 0;
+    auto take = [&](size_t b) { size_t r = off; off += align256(b); return r; };
+    const size_t o_best = take(L * 4), o_np = take(L * 4), o_st = take(L * 4),
+                 o_ps = take(L * K * 4), o_pr = take(L * K * 4), o_xyz = take(A * K * 12);
+    char *d = nullptr;
+    if (hipMalloc((void **)&d, off) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DOCK_ENOMEM, "autotune result allocation failed");
+    }
+    dock_results r{};
+    r.best_score = (float *)(d + o_best);
+    r.n_poses = (int32_t *)(d + o_np);
+    r.status = (int32_t *)(d + o_st);
+    r.pose_score = (float *)(d + o_ps);
+    r.pose_restart = (int32_t *)(d + o_pr);
+    r.pose_xyz = (float *)(d + o_xyz);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    auto body = [&]() -> int {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        Launch Lc;
+        int rc2 = prepare_launch(c, it->second, lib, p, &r, s, nullptr, false, &Lc);
+        if (rc2) return rc2;
+        const BinShape defaults[kNumBins] = {};
+        Shapes sh;
+        rc2 = make_shapes(c, Lc, defaults, &sh);
+        if (rc2) return rc2;
+        // one whole pass fills the workspace the stage kernels read
+        rc2 = run_sequence(c, Lc, sh, s, nullptr);
+        if (rc2) return rc2;
+        int counts[kNumBins];
+        HIP_TRY(hipMemcpyAsync(counts, Lc.wa.counters, sizeof(counts), hipMemcpyDeviceToHost, s));
+        HIP_TRY(hipStreamSynchronize(s));
+        const GridArgs &g = Lc.g;
+        const SearchArgs &sa = Lc.sa;
+        const LibArgs &la = Lc.la;
+        const WorkArgs &wa = Lc.wa;
+        const OutArgs &oa = Lc.oa;
+        // best of two timed runs of one stage launch (each stage's kernels only
+        // read what earlier stages wrote and rewrite the same values)
+        auto timeit = [&](auto &&launch, float *ms) -> int {
+            float best = 3.4e38f;
+            for (int rep = 0; rep < 2; ++rep) {
+                HIP_TRY(hipEventRecord(e0, s));
+                HIP_TRY(launch());
+                HIP_TRY(hipEventRecord(e1, s));
+                HIP_TRY(hipEventSynchronize(e1));
+                float t = 0.f;
+                HIP_TRY(hipEventElapsedTime(&t, e0, e1));
+                best = t < best ? t : best;
+            }
+            *ms = best;
+            return DOCK_OK;
+        };
+        std::array<BinShape, kNumBins> pick;
+        for (int bin = 0; bin < kNumBins; ++bin) pick[bin] = defaults[bin];
+        for (int bin = 0; bin < kNumBins; ++bin) {
+            if (counts[bin] <= 0) continue;
+            dock_bin_tuning rep{};
+            rep.ligands = counts[bin];
+            const BinShape def = defaults[bin];
+            BinShape &bs = pick[bin];
+            // torsion sweep: restarts (waves) per workgroup
+            float best = 3.4e38f;
+            for (int w : {2, 4, 8}) {
+                if (dock_lds_bytes(32 * (bin + 1), w) > (size_t)c->lds_arena) continue;
+                const int blocks = dock_blocks_per_cu(bin, w, sa.T) * c->num_cu;
+                float t = 0.f;
+                int e = timeit([&]() -> hipError_t {
+                    hipError_t q = launch_reset(wa.counters, kNumBins + bin, 1, s);
+                    return q ? q : launch_dock(bin, blocks, w, g, sa, la, wa, s);
+                }, &t);
+                if (e) return e;
+                if (w == def.dock_waves) rep.dock_ms_default = t;
+                if (t < best) { best = t; bs.dock_waves = w; }
+            }
+            rep.dock_ms = best;
+            // pose selection: waves per workgroup
+            best = 3.4e38f;
+            for (int w : {4, 8, 16}) {
+                int blocks = select_blocks_per_cu(bin, w, sa.R, sa.K) * c->num_cu;
+                blocks = blocks > la.L ? la.L : blocks;
+                float t = 0.f;
+                int e = timeit([&]() -> hipError_t {
+                    hipError_t q = launch_reset(wa.counters, 2 * kNumBins + bin, 1, s);
+                    return q ? q : launch_select(bin, blocks, w, g, sa, la, wa, oa, -1, s);
+                }, &t);
+                if (e) return e;
+                if (w == def.select_waves) rep.select_ms_default = t;
+                if (t < best) { best = t; bs.select_waves = w; }
+            }
+            rep.select_ms = best;
+            // final alignment: waves per workgroup and workgroups per CU
+            best = 3.4e38f;
+            for (int w : {2, 4, 8}) {
+                const int occ = falign_blocks_per_cu(bin, w);
+                for (int per : {1, 2, 4, 0}) {
+                    if (per >= occ) continue;  // same as 0 (all that fit)
+                    const int blocks = (per > 0 ? per : occ) * c->num_cu;
+                    float t = 0.f;
+                    int e = timeit([&]() -> hipError_t {
+                        return launch_falign(bin, blocks, w, g, sa, la, wa, oa, -1, s);
+                    }, &t);
+                    if (e) return e;
+                    if (w == def.falign_waves && per == def.falign_per_cu) rep.falign_ms_default = t;
+                    if (t < best) { best = t; bs.falign_waves = w; bs.falign_per_cu = per; }
+                }
+            }
+            rep.falign_ms = best;
+            rep.dock_waves = bs.dock_waves;
+            rep.select_waves = bs.select_waves;
+            rep.falign_waves = bs.falign_waves;
+            rep.falign_per_cu = bs.falign_per_cu;
+            if (out) out[bin] = rep;
+        }
+        c->tuned[tune_key(sa)] = pick;
+        return DOCK_OK;
+    };
+    const int rc3 = body();
+    (void)hipStreamSynchronize(s);
+    if (e0) (void)hipEventDestroy(e0);
+    if (e1) (void)hipEventDestroy(e1);
+    (void)hipFree(d);
+    return rc3;
+}
+
+int dock_set_tuning(dock_ctx *c, const dock_params *p, const dock_bin_tuning *table) {
+    if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
+    const int rc = check_params(p);
+    if (rc) return rc;
+    std::lock_guard<std::mutex> lk(c->mu);
+    SearchArgs sa{};
+    sa.R = p->restarts;
+    sa.T = p->torsion_steps;
+    sa.A = p->align_steps;
+    sa.K = p->top_k;
+    sa.P = p->sweep_passes;
+    if (!table) {
+        c->tuned.erase(tune_key(sa));
+        return DOCK_OK;
+    }
+    std::array<BinShape, kNumBins> pick;
+    for (int bin = 0; bin < kNumBins; ++bin) {
+        const dock_bin_tuning &t = table[bin];
+        BinShape b;
+        if (t.ligands > 0) {
+            if (t.dock_waves < 1 || t.dock_waves > 8 ||
+                dock_lds_bytes(32 * (bin + 1), t.dock_waves) > (size_t)c->lds_arena)
+                return fail(DOCK_EINVAL, "dock_waves must be in [1,8] and fit the LDS");
+            if (t.select_waves < 1 || t.select_waves > 16)
+                return fail(DOCK_EINVAL, "select_waves must be in [1,16]");
+            if (t.falign_waves < 1 || t.falign_waves > 8)
+                return fail(DOCK_EINVAL, "falign_waves must be in [1,8]");
+            if (t.falign_per_cu < 0) return fail(DOCK_EINVAL, "falign_per_cu must be >= 0");
+            b.dock_waves = t.dock_waves;
+            b.select_waves = t.select_waves;
+            b.falign_waves = t.falign_waves;
+            b.falign_per_cu = t.falign_per_cu;
+        }
+        pick[bin] = b;
+    }
+    c->tuned[tune_key(sa)] = pick;
+    return DOCK_OK;
 }
 
 int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock_params *p,

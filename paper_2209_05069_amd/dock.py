@@ -57,6 +57,18 @@ class Results(ctypes.Structure):
                 ("final_trace", P)]
 
 
+class BinTuning(ctypes.Structure):
+    _fields_ = [("ligands", ctypes.c_int32), ("dock_waves", ctypes.c_int32),
+                ("select_waves", ctypes.c_int32), ("falign_waves", ctypes.c_int32),
+                ("falign_per_cu", ctypes.c_int32), ("dock_ms", ctypes.c_float),
+                ("select_ms", ctypes.c_float), ("falign_ms", ctypes.c_float),
+                ("dock_ms_default", ctypes.c_float), ("select_ms_default", ctypes.c_float),
+                ("falign_ms_default", ctypes.c_float)]
+
+
+NUM_BINS = 8
+
+
 class Timing(ctypes.Structure):
     _fields_ = [("prep_ms", ctypes.c_double), ("dock_ms", ctypes.c_double),
                 ("align_ms", ctypes.c_double), ("final_ms", ctypes.c_double),
@@ -64,9 +76,9 @@ class Timing(ctypes.Structure):
                 ("scored_samples", ctypes.c_int64)]
 
 
-EXPORTS = ["dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
+EXPORTS = ["dock_autotune", "dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
            "dock_ligands_batch", "dock_ligands_batch_noalloc", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
-           "dock_request_bytes", "dock_set_timing", "dock_submit", "dock_wait"]
+           "dock_request_bytes", "dock_set_timing", "dock_set_tuning", "dock_submit", "dock_wait"]
 
 _lib = None
 
@@ -98,6 +110,9 @@ def lib():
         L.dock_request_bytes.argtypes = [ctypes.POINTER(Library), ctypes.POINTER(Params),
                                          ctypes.POINTER(Results), ctypes.POINTER(ctypes.c_uint64)]
         L.dock_wait.argtypes = [P, ctypes.c_uint64]
+        L.dock_autotune.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
+                                    ctypes.POINTER(Params), ctypes.POINTER(BinTuning), P]
+        L.dock_set_tuning.argtypes = [P, ctypes.POINTER(Params), ctypes.POINTER(BinTuning)]
         L.dock_set_timing.argtypes = [P, ctypes.c_int]
         L.dock_get_timing.argtypes = [P, ctypes.POINTER(Timing)]
         _lib = L
@@ -345,6 +360,36 @@ def dock_poll(ctx, ticket: int) -> bool:
 
 def dock_wait(ctx, ticket: int):
     _check(lib().dock_wait(ctx, ticket))
+
+
+_TUNE_FIELDS = [f[0] for f in BinTuning._fields_]
+
+
+def dock_autotune(ctx, pocket: int, dlib: DeviceLibrary, params: SearchParams, stream=None):
+    """Tune the batched tiles per size bin on a device-resident sample; returns the
+    per-bin table (list of dicts, see include/dock.h)."""
+    if stream is None:
+        import torch
+        stream = torch.cuda.current_stream().cuda_stream
+    elif hasattr(stream, "cuda_stream"):
+        stream = stream.cuda_stream
+    out = (BinTuning * NUM_BINS)()
+    _check(lib().dock_autotune(ctx, pocket, ctypes.byref(dlib.s), ctypes.byref(params.s), out,
+                               ctypes.c_void_p(stream)))
+    return [{k: getattr(t, k) for k in _TUNE_FIELDS} for t in out]
+
+
+def dock_set_tuning(ctx, params: SearchParams, table=None):
+    """Use `table` (as returned by dock_autotune) for these search settings; None
+    restores the default tiles."""
+    if table is None:
+        _check(lib().dock_set_tuning(ctx, ctypes.byref(params.s), None))
+        return
+    arr = (BinTuning * NUM_BINS)()
+    for i, t in enumerate(table):
+        for k in _TUNE_FIELDS:
+            setattr(arr[i], k, t.get(k, 0))
+    _check(lib().dock_set_tuning(ctx, ctypes.byref(params.s), arr))
 
 
 def dock_set_timing(ctx, enable: bool):

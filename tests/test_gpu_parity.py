@@ -454,3 +454,44 @@ def test_serving_loop_maps_results_to_requests(D, ctx):
         for req in reqs:
             if req.pocket == p:
                 assert srv.results[req.rid] == h["best_score"][req.ligand], req
+
+
+def test_autotune_reports_every_bin_and_keeps_results(D, ctx):
+    """The per-bin tile choice changes only launch shapes: results stay bitwise
+    equal to the default tiles, for the tuned table and for a forced one."""
+    pk, lib, q, s = synth.config(2, n_ligands=400)
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    params = D.SearchParams(q, **s)
+    dl = D.DeviceLibrary(lib)
+    print(f"[case] autotune, {lib.n_ligands} paper-scale ligands", flush=True)
+
+    def run():
+        res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params,
+                              restart_scores=True, trace=True, final_trace=True)
+        D.dock_ligands_batch(ctx, pid, dl, params, res)
+        torch.cuda.synchronize()
+        return res.to_host()
+
+    D.dock_set_tuning(ctx, params, None)
+    h0 = run()
+    table = D.dock_autotune(ctx, pid, dl, params)
+    print(f"[tuning] {table}", flush=True)
+    expect = np.bincount((lib.n_atoms() - 1) // 32, minlength=8)
+    assert [t["ligands"] for t in table] == list(expect)
+    for t in table:
+        if t["ligands"] == 0:
+            continue
+        assert t["dock_waves"] in (2, 4, 8) and t["select_waves"] in (4, 8, 16)
+        assert t["falign_waves"] in (2, 4, 8) and t["falign_per_cu"] in (0, 1, 2, 4)
+        for k in ("dock", "select", "falign"):
+            assert 0 < t[f"{k}_ms"] <= t[f"{k}_ms_default"]
+    h1 = run()
+    forced = [dict(t, dock_waves=8, select_waves=16, falign_waves=2, falign_per_cu=1)
+              if t["ligands"] else t for t in table]
+    D.dock_set_tuning(ctx, params, forced)
+    h2 = run()
+    D.dock_set_tuning(ctx, params, None)
+    for h in (h1, h2):
+        for k, a in h0.items():
+            assert np.array_equal(a, h[k]), k
+    D.dock_pocket_unload(ctx, pid)
