@@ -105,6 +105,28 @@ int dock_pocket_load(dock_ctx *ctx, const dock_grid_desc *grid, int32_t *pocket_
 /* DOCK_EBUSY while dock_submit work that uses the pocket is not finished. */
 int dock_pocket_unload(dock_ctx *ctx, int32_t pocket_id);
 
+/* Pocket atoms for the pairwise rescoring stand-in.  The paper's Rescore Pose
+ * evaluates every ligand atom against every pocket atom and accumulates the pair
+ * terms per pose (Rescore Pose subsections of the latency and batched
+ * implementations); its chemical terms are not given, so here the contact score
+ * of a pose is the sum over ligand atoms i and pocket atoms j with
+ * |x_i - p_j| < contact_dist of weight[type_i * ntypes + type_j] (type_i: the
+ * ligand atom's grid type; an integer).  Host memory, copied before the call
+ * returns; replaces the pocket's previous atom list.  Requires ntypes in
+ * [1,255], types < ntypes, finite coordinates, 0 < contact_dist <= 1000 and
+ * (grid ntypes) * ntypes <= 1024.  DOCK_EBUSY while dock_submit work that uses
+ * the pocket is not finished; waits for the device's other work. */
+typedef struct {
+    int32_t n_atoms;
+    int32_t ntypes;            /* pocket atom types */
+    float contact_dist;        /* Angstrom */
+    const float *xyz;          /* [n_atoms][3], the grid's frame, Angstrom */
+    const uint8_t *type;       /* [n_atoms] */
+    const int32_t *weight;     /* [grid ntypes][ntypes] */
+} dock_pocket_atoms;
+
+int dock_pocket_set_atoms(dock_ctx *ctx, int32_t pocket_id, const dock_pocket_atoms *atoms);
+
 /* Ligand library in CSR form (paper: coordinates, atom types and the fragments
  * of the rotatable bonds; Batched Implementation subsection).  Ligand l owns
  * atoms [atom_off[l], atom_off[l+1]), bonds [bond_off[l], bond_off[l+1]) and
@@ -174,10 +196,14 @@ typedef struct {
  *     R*(l + P*rot_off[l]) and holds, per restart, 1 + P*B_l entries: the
  *     alignment index o, then the applied torsion step of each decision
  *     (DOCK_TRACE_NONE when every candidate bumped);
- *   final_trace[l*K + s]: alignment index of the final step (0 if final_align=0).
+ *   final_trace[l*K + s]: alignment index of the final step (0 if final_align=0);
+ *   pose_contacts[l*K + s]: contact score of output pose s against the pocket's
+ *     atoms (dock_pocket_set_atoms; the call fails with DOCK_EINVAL when the
+ *     pocket has none); 0 for slots s >= n_poses[l].
  * For a ligand whose status is not DOCK_LIG_OK only best_score (-inf), n_poses
  * (0), status, pose_score (-inf), pose_restart (-1) and final_trace (0) are
- * written; its pose_xyz, restart_score and trace entries are left as they were. */
+ * written (and pose_contacts, 0); its pose_xyz, restart_score and trace entries
+ * are left as they were. */
 typedef struct {
     float *best_score;        /* [L] */
     int32_t *n_poses;         /* [L] */
@@ -188,6 +214,7 @@ typedef struct {
     float *restart_score;     /* [L*R] or NULL */
     uint16_t *trace;          /* [R*(L + P*n_rot_total)] or NULL */
     uint16_t *final_trace;    /* [L*K] or NULL */
+    int32_t *pose_contacts;   /* [L*K] or NULL */
 } dock_results;
 
 /* Dock a device-resident library; all work is enqueued on `stream` (a
@@ -255,7 +282,8 @@ int dock_wait(dock_ctx *ctx, uint64_t ticket);
  * then times the torsion-sweep kernel with 2, 4 and 8 restarts (waves) per
  * workgroup, the pose-selection kernel with 4, 8 and 16 waves per workgroup,
  * and the final-alignment kernel with 2, 4 and 8 waves per workgroup at 1, 2,
- * 4 or all workgroups per CU that fit, each the best of two runs on `stream`;
+ * 4 or all workgroups per CU that fit, with and without the per-XCD split of
+ * the ligands, each the best of two runs on `stream`;
  * the fastest tile of each kernel is kept by the context for these search
  * settings (restarts, torsion_steps, align_steps, top_k, sweep_passes) and used
  * by every later batched call with them (results do not depend on the tiles).
@@ -269,6 +297,10 @@ typedef struct {
     int32_t select_waves;    /* pose selection: waves per workgroup */
     int32_t falign_waves;    /* final alignment: waves per workgroup */
     int32_t falign_per_cu;   /* final alignment: workgroups per CU (0: all that fit) */
+    int32_t falign_xcd;      /* final alignment: 1 = the ligands are split into 8 contiguous
+                                shares, one per XCD (workgroups go round-robin to the
+                                8 XCDs), so a ligand's kept poses share one L2; 0 = the
+                                grid's waves take (ligand, pose) items in turn */
     float dock_ms, select_ms, falign_ms;  /* the chosen tiles on the sample */
     float dock_ms_default, select_ms_default, falign_ms_default;  /* the default tiles
                                                 (4, 4, 4 waves, all that fit) */

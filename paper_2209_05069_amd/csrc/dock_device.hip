@@ -1895,7 +1895,7 @@ size_t falign_lds_bytes(int nmax, int waves, int single) {
 template <int NS>
 __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibArgs lib,
                                                WorkArgs ws, const int *__restrict__ status,
-                                               int bin, int single) {
+                                               int bin, int single, int xcds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     // every lane is active here, so the wave index is read from the first lane
@@ -1915,11 +1915,20 @@ __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibAr
     // items in turn (item = global wave index + k * waves in the grid).  The
     // item index is scalar arithmetic only: no lane-dependent branch precedes
     // the loop test, so every lane of a wave runs the same items.
+    // With xcds > 1 the workgroups are taken as dispatched round-robin over that
+    // many XCDs (workgroup b on XCD b % xcds): XCD x takes a contiguous x-th share
+    // of the bin's ligands, so the kept poses of a ligand share one L2.
     float4 *rec = (float4 *)(smem + (size_t)wave * nmax * 16);
-    const long long total = (long long)ws.counters[bin] * sa.K;
-    const long long nwaves = (long long)gridDim.x * W;
-    for (long long item = (long long)blockIdx.x * W + wave; item < total; item += nwaves) {
-        const int li = (int)(item / sa.K), s = (int)(item - (long long)li * sa.K);
+    const long long nl = ws.counters[bin];
+    const int x = xcds > 1 ? (int)(blockIdx.x % xcds) : 0;
+    const int bx = xcds > 1 ? (int)(blockIdx.x / xcds) : (int)blockIdx.x;
+    const int nbx = xcds > 1 ? (int)((gridDim.x - x + xcds - 1) / xcds) : (int)gridDim.x;
+    const int nx = xcds > 1 ? xcds : 1;
+    const long long li0 = nl * x / nx, li1 = nl * (x + 1) / nx;
+    const long long total = (li1 - li0) * sa.K;
+    const long long nwaves = (long long)nbx * W;
+    for (long long item = (long long)bx * W + wave; item < total; item += nwaves) {
+        const int li = (int)(li0 + item / sa.K), s = (int)(item % sa.K);
         const int l = ws.bin_list[(size_t)bin * lib.L + li];
         if (s < ws.nsel[l]) final_item<NS>(l, s, rec, tr, g, sa, lib, ws, WaveSplit(), true);
     }
@@ -1996,6 +2005,101 @@ __global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArg
             if (ns == 0) out.best[l] = -INFINITY;
         }
         __syncthreads();
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Pairwise rescoring stand-in (Rescore Pose): the paper evaluates every ligand
+// atom against every pocket atom and accumulates the pair terms per pose; here
+// the pair term is weight[ligand type][pocket atom type] for pairs closer than
+// the contact distance, summed as an integer.  Pairs beyond the neighbouring
+// cells of the pocket-atom cell grid are farther apart than the contact
+// distance, so only the 3 x 3 rows of 3 cells around the atom are visited.
+
+__device__ __forceinline__ int wave_sum_int(int v) {
+    v += dpp_read<0x111, 0xf>(v);  // row_shr:1
+    v += dpp_read<0x112, 0xf>(v);  // row_shr:2
+    v += dpp_read<0x114, 0xf>(v);  // row_shr:4
+    v += dpp_read<0x118, 0xf>(v);  // row_shr:8
+    v += dpp_read<0x142, 0xa>(v);  // row_bcast:15
+    v += dpp_read<0x143, 0xc>(v);  // row_bcast:31
+    return __builtin_amdgcn_readlane(v, 63);
+}
+
+__device__ int atom_contacts(const ContactArgs &ca, const int *wrow, float px, float py,
+                             float pz) {
+    // cell of the atom; coordinates are clamped to one cell beyond the grid, which
+    // only adds pocket atoms that fail the distance test
+    const float fx = fminf(fmaxf((px - ca.lox) * ca.inv_cell, -1.f), (float)ca.cx);
+    const float fy = fminf(fmaxf((py - ca.loy) * ca.inv_cell, -1.f), (float)ca.cy);
+    const float fz = fminf(fmaxf((pz - ca.loz) * ca.inv_cell, -1.f), (float)ca.cz);
+    const int ix = (int)floorf(fx), iy = (int)floorf(fy), iz = (int)floorf(fz);
+    const int x0 = ix - 1 < 0 ? 0 : ix - 1, x1 = ix + 1 >= ca.cx ? ca.cx - 1 : ix + 1;
+    int v = 0;
+    if (x0 > x1) return 0;
+    for (int z = iz - 1; z <= iz + 1; ++z) {
+        if (z < 0 || z >= ca.cz) continue;
+        for (int y = iy - 1; y <= iy + 1; ++y) {
+            if (y < 0 || y >= ca.cy) continue;
+            const int row = (z * ca.cy + y) * ca.cx;
+            const int j1 = ca.cell_start[row + x1 + 1];
+            for (int j = ca.cell_start[row + x0]; j < j1; ++j) {
+                const float4 a = ca.atoms[j];
+                const float dx = px - a.x, dy = py - a.y, dz = pz - a.z;
+                const float d2 = fmaf(dx, dx, fmaf(dy, dy, dz * dz));
+                if (d2 < ca.dc2) v += wrow[__float_as_int(a.w)];
+            }
+        }
+    }
+    return v;
+}
+
+__global__ __launch_bounds__(256) void k_rescore(ContactArgs ca, SearchArgs sa, LibArgs lib,
+                                                 OutArgs out, int single) {
+    __shared__ int wt[kMaxContactWeights];
+    __shared__ int part[4];
+    for (int e = threadIdx.x; e < ca.nw; e += blockDim.x) wt[e] = ca.weight[e];
+    __syncthreads();
+    const int K = sa.K;
+    // every lane is active here, so the wave index is read from the first lane
+    const int W = blockDim.x >> 6, wave = uniform_int((int)(threadIdx.x >> 6)), lane = lane_id();
+    if (single >= 0) {
+        // plain form: workgroup s scores output pose s of the ligand, its threads
+        // over the ligand's atoms
+        const int l = single, s = blockIdx.x;
+        int v = 0;
+        if (s < out.npose[l]) {
+            const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+            const float *P = out.pxyz + ((size_t)a0 * K + (size_t)s * n) * 3;
+            for (int i = threadIdx.x; i < n; i += blockDim.x)
+                v += atom_contacts(ca, wt + (int)lib.type[a0 + i] * ca.ntypes, P[3 * i],
+                                   P[3 * i + 1], P[3 * i + 2]);
+        }
+        v = wave_sum_int(v);
+        if (lane == 0) part[wave] = v;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+            int t = 0;
+            for (int w = 0; w < W; ++w) t += part[w];
+            out.pcontacts[(size_t)l * K + s] = t;
+        }
+        return;
+    }
+    // batched form: the grid's waves take the (ligand, output pose) items in turn
+    const long long total = (long long)lib.L * K;
+    const long long nwaves = (long long)gridDim.x * W;
+    for (long long item = (long long)blockIdx.x * W + wave; item < total; item += nwaves) {
+        const int l = (int)(item / K), s = (int)(item - (long long)l * K);
+        int v = 0;
+        if (s < out.npose[l]) {
+            const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
+            const float *P = out.pxyz + ((size_t)a0 * K + (size_t)s * n) * 3;
+            for (int i = lane; i < n; i += 64)
+                v += atom_contacts(ca, wt + (int)lib.type[a0 + i] * ca.ntypes, P[3 * i],
+                                   P[3 * i + 1], P[3 * i + 2]);
+        }
+        v = wave_sum_int(v);
+        if (lane == 0) out.pcontacts[item] = v;
     }
 }
 
@@ -2138,6 +2242,14 @@ __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs 
         }
     }
     if (lane == 0) out.status[l] = status;
+}
+
+hipError_t launch_rescore(const ContactArgs &ca, const SearchArgs &sa, const LibArgs &lib,
+                          const OutArgs &out, int single, int blocks, hipStream_t s) {
+    if (single >= 0) blocks = sa.K;
+    if (blocks <= 0) return hipSuccess;
+    hipLaunchKernelGGL(k_rescore, dim3(blocks), dim3(256), 0, s, ca, sa, lib, out, single);
+    return hipGetLastError();
 }
 
 // Zero counters [first, first + count) (count <= 64): work-queue counters are
@@ -2286,23 +2398,23 @@ hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, cons
 template <int NS>
 static hipError_t launch_falign_t(int bin, int blocks, int waves, const GridArgs &g,
                                   const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
-                                  const OutArgs &out, int single, hipStream_t s) {
+                                  const OutArgs &out, int single, int xcds, hipStream_t s) {
     const size_t lds = falign_lds_bytes(bin_nmax(bin), waves, single >= 0 ? 1 : 0);
     hipFuncSetAttribute((const void *)k_falign<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     hipLaunchKernelGGL((k_falign<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws,
-                       (const int *)out.status, bin, single);
+                       (const int *)out.status, bin, single, xcds);
     return hipGetLastError();
 }
 
 hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                          const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         hipStream_t s) {
+                         int xcds, hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_falign_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 2: return launch_falign_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 3: return launch_falign_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        default: return launch_falign_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 1: return launch_falign_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        case 2: return launch_falign_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        case 3: return launch_falign_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        default: return launch_falign_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
     }
 }
 

@@ -14,6 +14,7 @@ constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, select_next, align_next
 constexpr int kMaxTopK = 64;        // matches DOCK_MAX_TOP_K
+constexpr int kXcds = 8;            // gfx950: workgroups go round-robin to 8 XCDs of 32 CUs
 constexpr int kAlignJ = 32;         // k_align: y rotations per lane
 constexpr int kAlignMaxGroup = 64;  // k_align: restarts per item at most
 
@@ -82,6 +83,21 @@ struct WorkArgs {
     unsigned long long *scored;  // torsion samples scored (measurement; null: not counted)
 };
 
+// Pocket atoms of the pairwise rescoring stand-in, sorted into a cell grid whose
+// cell edge is at least the contact distance (plus a margin above rounding), so
+// every contact pair lies in neighbouring cells.
+constexpr int kMaxContactWeights = 1024;  // ligand types x pocket atom types
+struct ContactArgs {
+    const float4 *atoms;     // [n] (x, y, z, type as int bits), sorted by cell
+    const int *cell_start;   // [cx*cy*cz + 1] first atom of each cell (x fastest)
+    const int *weight;       // [ligand types][ntypes]
+    int ntypes, nw;          // pocket atom types; weight entries
+    int cx, cy, cz;          // cells per axis
+    float lox, loy, loz;     // corner of cell (0,0,0)
+    float inv_cell;          // 1 / cell edge
+    float dc2;               // contact distance squared
+};
+
 struct OutArgs {
     float *best;
     int *npose;
@@ -91,6 +107,7 @@ struct OutArgs {
     float *pxyz;
     float *rscore_user;       // optional copy of restart scores
     uint16_t *ftrace;         // optional
+    int *pcontacts;           // optional: contact score of each output pose
 };
 
 // Shared-memory bytes of the docking kernel for a bin with at most nmax atoms
@@ -132,11 +149,18 @@ int align_blocks_per_cu(int bin, int R, int A, int arena);
 hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                          const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
                          hipStream_t s);
+// xcds > 1: the bin's ligands are split into that many contiguous shares, share x
+// taken by workgroups b with b % xcds == x (the XCD they are dispatched to).
 hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
                          const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         hipStream_t s);
+                         int xcds, hipStream_t s);
 hipError_t launch_out(int bin, int blocks, const SearchArgs &sa, const LibArgs &lib,
                       const WorkArgs &ws, const OutArgs &out, int single, hipStream_t s);
+// Contact score (pairwise rescoring stand-in) of every output pose: single >= 0:
+// ligand `single` only, one workgroup per pose (grid top_k); else every ligand,
+// one wave per (ligand, pose) over `blocks` workgroups.
+hipError_t launch_rescore(const ContactArgs &ca, const SearchArgs &sa, const LibArgs &lib,
+                          const OutArgs &out, int single, int blocks, hipStream_t s);
 // Plain form: checks of ligand l only (no size binning), and its restarts
 // (grid = R workgroups of `waves` waves).
 hipError_t launch_prep_one(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,

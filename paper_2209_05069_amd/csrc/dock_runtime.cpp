@@ -76,13 +76,23 @@ struct Pocket {
     float4 *d_atlas = nullptr;
     int4 *d_bands = nullptr;
     int *d_blob16 = nullptr;
+    void *d_contacts = nullptr;  // pocket atoms, cell starts and weights (rescoring)
     GridArgs g{};
+    ContactArgs ca{};
+    bool has_atoms = false;
     int busy = 0;
+    void release_atoms() {
+        hipFree(d_contacts);
+        d_contacts = nullptr;
+        has_atoms = false;
+        ca = ContactArgs{};
+    }
     void release() {
         hipFree(d_cubes);
         hipFree(d_atlas);
         hipFree(d_bands);
         hipFree(d_blob16);
+        release_atoms();
         d_cubes = d_atlas = nullptr;
         d_bands = nullptr;
         d_blob16 = nullptr;
@@ -108,6 +118,7 @@ struct BinShape {
     int select_waves = 4;   // k_select: waves per workgroup
     int falign_waves = 4;   // k_falign: waves per workgroup
     int falign_per_cu = 0;  // k_falign: workgroups per CU (0: as many as fit)
+    int falign_xcd = 0;     // k_falign: 1 = each XCD takes a contiguous share of ligands
 };
 
 // Host image of a Tables allocation (offsets relative to its start).
@@ -128,7 +139,7 @@ struct Ticket {
     hipStream_t stream = nullptr;    // submit stream the request runs on
     size_t stage_bytes = 0;
     // offsets of the result arrays inside host_stage
-    size_t o_best, o_np, o_st, o_ps, o_pr, o_xyz, o_rs, o_tr, o_ft;
+    size_t o_best, o_np, o_st, o_ps, o_pr, o_xyz, o_rs, o_tr, o_ft, o_pc;
 };
 
 }  // namespace
@@ -410,6 +421,7 @@ SubmitLayout submit_layout(const dock_library *lib, const dock_params *p, const 
     t->o_rs = stake(o->restart_score ? (size_t)L * R * 4 : 0);
     t->o_tr = stake((size_t)trace_len * 2);
     t->o_ft = stake(o->final_trace ? (size_t)L * K * 2 : 0);
+    t->o_pc = stake(o->pose_contacts ? (size_t)L * K * 4 : 0);
     t->stage_bytes = so;
     sl.results = so;
     return sl;
@@ -436,7 +448,7 @@ constexpr int kPlainStreams = 4;
 // The host needs each ligand's size to pick the kernel, so the offsets are read
 // back first (this form is synchronous with respect to the host anyway).
 int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const SearchArgs &sa,
-                  const LibArgs &la, const WorkArgs &wa, const OutArgs &oa,
+                  const LibArgs &la, const WorkArgs &wa, const OutArgs &oa, const ContactArgs &ca,
                   const std::array<hipEvent_t, 5> &ev, hipStream_t s) {
     const int L = lib->n_ligands;
     std::vector<int32_t> ao(L + 1);
@@ -466,8 +478,9 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
         const int bin = (n - 1) >> 5;
         HIP_TRY(launch_plain(l, bin, kPlainWaves, g, sa, la, wa, oa, t));
         HIP_TRY(launch_select(bin, 1, kPlainSelectWaves, g, sa, la, wa, oa, l, t));
-        HIP_TRY(launch_falign(bin, sa.K, kPlainFalignWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_falign(bin, sa.K, kPlainFalignWaves, g, sa, la, wa, oa, l, 0, t));
         HIP_TRY(launch_out(bin, 1, sa, la, wa, oa, l, t));
+        if (oa.pcontacts) HIP_TRY(launch_rescore(ca, sa, la, oa, l, 0, t));
     }
     for (size_t i = 0; i < c->plain_streams.size(); ++i) {
         HIP_TRY(hipEventRecord(c->plain_events[i], c->plain_streams[i]));
@@ -496,6 +509,7 @@ struct Launch {
     LibArgs la;
     WorkArgs wa;
     OutArgs oa;
+    ContactArgs ca;
 };
 
 // Tables, workspace and kernel arguments of a call on a device-resident library
@@ -503,6 +517,8 @@ struct Launch {
 // workspace are placed in that buffer and nothing is allocated on the device.
 int prepare_launch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const dock_params *p,
                    const dock_results *o, hipStream_t s, char *scratch, bool timed, Launch *L) {
+    if (o->pose_contacts && !pk.has_atoms)
+        return fail(DOCK_EINVAL, "pose_contacts needs the pocket's atoms (dock_pocket_set_atoms)");
     Tables tb;
     const bool user_trace = o->trace != nullptr;
     const WsLayout wl = ws_layout(lib, p, user_trace);
@@ -592,6 +608,8 @@ int prepare_launch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const
     oa.pxyz = o->pose_xyz;
     oa.rscore_user = o->restart_score;
     oa.ftrace = o->final_trace;
+    oa.pcontacts = o->pose_contacts;
+    if (pk.has_atoms) std::memcpy((void *)&L->ca, (const void *)&pk.ca, sizeof(ContactArgs));
     return DOCK_OK;
 }
 
@@ -601,7 +619,7 @@ struct Shapes {
     BinShape tile[kNumBins];
     int align_blocks[kNumBins], dock_blocks[kNumBins], select_blocks[kNumBins],
         falign_blocks[kNumBins];
-    int out_blocks;
+    int out_blocks, rescore_blocks;
 };
 
 std::string tune_key(const SearchArgs &sa) {
@@ -635,6 +653,9 @@ int make_shapes(dock_ctx *c, const Launch &L, const BinShape *tile, Shapes *sh) 
         sh->falign_blocks[bin] = per_cu * c->num_cu;
     }
     sh->out_blocks = std::min(L.la.L, kOutBlocksPerCu * c->num_cu);
+    // rescoring: 4 waves per workgroup, at most one wave per (ligand, pose) item
+    sh->rescore_blocks =
+        (int)std::min<long long>(((long long)L.la.L * L.sa.K + 3) / 4, 8LL * c->num_cu);
     return DOCK_OK;
 }
 
@@ -662,9 +683,10 @@ int run_sequence(dock_ctx *c, const Launch &L, const Shapes &sh, hipStream_t s,
                               oa, -1, s));
     for (int bin = 0; bin < kNumBins; ++bin)
         HIP_TRY(launch_falign(bin, sh.falign_blocks[bin], sh.tile[bin].falign_waves, g, sa, la, wa,
-                              oa, -1, s));
+                              oa, -1, sh.tile[bin].falign_xcd ? kXcds : 0, s));
     for (int bin = 0; bin < kNumBins; ++bin)
         HIP_TRY(launch_out(bin, sh.out_blocks, sa, la, wa, oa, -1, s));
+    if (oa.pcontacts) HIP_TRY(launch_rescore(L.ca, sa, la, oa, -1, sh.rescore_blocks, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[4], s));
     return DOCK_OK;
 }
@@ -692,7 +714,8 @@ int enqueue_batch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const 
         for (auto &e : ev) HIP_TRY(hipEventCreate(&e));
         c->marks.push_back(ev);
     }
-    if (p->mode == DOCK_MODE_PLAIN) return enqueue_plain(c, lib, L.g, L.sa, L.la, L.wa, L.oa, ev, s);
+    if (p->mode == DOCK_MODE_PLAIN)
+        return enqueue_plain(c, lib, L.g, L.sa, L.la, L.wa, L.oa, L.ca, ev, s);
     // launch shapes (occupancy queries stay outside any graph capture)
     Shapes sh;
     rc = make_shapes(c, L, bin_tiles(c, L.sa), &sh);
@@ -930,6 +953,108 @@ int dock_pocket_unload(dock_ctx *c, int32_t pocket_id) {
     return DOCK_OK;
 }
 
+int dock_pocket_set_atoms(dock_ctx *c, int32_t pocket_id, const dock_pocket_atoms *pa) {
+    if (!c || !pa) return fail(DOCK_EINVAL, "NULL argument");
+    if (pa->n_atoms < 0 || pa->n_atoms >= (1 << 24)) return fail(DOCK_EINVAL, "n_atoms must be in [0, 2^24)");
+    if (pa->ntypes < 1 || pa->ntypes > 255) return fail(DOCK_EINVAL, "ntypes must be in [1,255]");
+    if (!(pa->contact_dist > 0.f) || !std::isfinite(pa->contact_dist) || pa->contact_dist > 1e3f)
+        return fail(DOCK_EINVAL, "contact_dist must be in (0, 1000] Angstrom");
+    if (!pa->weight || (pa->n_atoms > 0 && (!pa->xyz || !pa->type)))
+        return fail(DOCK_EINVAL, "xyz/type/weight is NULL");
+    std::lock_guard<std::mutex> lk(c->mu);
+    auto it = c->pockets.find(pocket_id);
+    if (it == c->pockets.end()) return fail(DOCK_ENOENT, "unknown pocket");
+    Pocket &pk = it->second;
+    if (pk.busy) return fail(DOCK_EBUSY, "pocket has submitted work in flight");
+    const int lt = pk.g.ntypes, nw = lt * pa->ntypes;
+    if (nw > kMaxContactWeights)
+        return fail(DOCK_EINVAL, "grid types x pocket atom types must be <= 1024");
+    const int n = pa->n_atoms;
+    double lo[3] = {0, 0, 0}, hi[3] = {0, 0, 0};
+    for (int i = 0; i < n; ++i) {
+        if (pa->type[i] >= pa->ntypes) return fail(DOCK_EINVAL, "pocket atom type >= ntypes");
+        for (int a = 0; a < 3; ++a) {
+            const double v = pa->xyz[3 * i + a];
+            if (!std::isfinite(v)) return fail(DOCK_EINVAL, "pocket atom coordinate not finite");
+            lo[a] = i == 0 || v < lo[a] ? v : lo[a];
+            hi[a] = i == 0 || v > hi[a] ? v : hi[a];
+        }
+    }
+    // cell edge: the contact distance plus a margin far above FP32 rounding of the
+    // coordinates, grown if the grid would exceed 2^22 cells
+    double h = (double)pa->contact_dist + 1e-3;
+    long long dims[3];
+    for (;;) {
+        long long cells = 1;
+        for (int a = 0; a < 3; ++a) {
+            dims[a] = (long long)std::floor((hi[a] - lo[a]) / h) + 1;
+            cells *= dims[a];
+        }
+        if (cells <= (1LL << 22)) break;
+        h *= 1.25;
+    }
+    const long long ncell = dims[0] * dims[1] * dims[2];
+    std::vector<int> cell_of(n), start(ncell + 1, 0);
+    for (int i = 0; i < n; ++i) {
+        long long ci[3];
+        for (int a = 0; a < 3; ++a) {
+            ci[a] = (long long)std::floor(((double)pa->xyz[3 * i + a] - lo[a]) / h);
+            ci[a] = ci[a] < 0 ? 0 : (ci[a] >= dims[a] ? dims[a] - 1 : ci[a]);
+        }
+        cell_of[i] = (int)((ci[2] * dims[1] + ci[1]) * dims[0] + ci[0]);
+        start[cell_of[i] + 1] += 1;
+    }
+    for (long long cidx = 0; cidx < ncell; ++cidx) start[cidx + 1] += start[cidx];
+    std::vector<float4> atoms((size_t)(n > 0 ? n : 1));
+    {
+        std::vector<int> fill(start.begin(), start.end() - 1);
+        for (int i = 0; i < n; ++i) {
+            int t = pa->type[i];
+            float tw;
+            std::memcpy(&tw, &t, sizeof(tw));
+            atoms[(size_t)fill[cell_of[i]]++] =
+                make_float4(pa->xyz[3 * i], pa->xyz[3 * i + 1], pa->xyz[3 * i + 2], tw);
+        }
+    }
+    const size_t b_atoms = align256(atoms.size() * sizeof(float4)),
+                 b_start = align256((size_t)(ncell + 1) * sizeof(int)),
+                 b_w = align256((size_t)nw * sizeof(int));
+    HIP_TRY(hipSetDevice(c->device));
+    HIP_TRY(hipDeviceSynchronize());  // no dock_ligands_batch work reads the old list
+    void *d = nullptr;
+    if (hipMalloc(&d, b_atoms + b_start + b_w) != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(DOCK_ENOMEM, "pocket atom allocation failed");
+    }
+    hipError_t e = hipMemcpy(d, atoms.data(), atoms.size() * sizeof(float4), hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy((char *)d + b_atoms, start.data(), (size_t)(ncell + 1) * sizeof(int),
+                          hipMemcpyHostToDevice);
+    if (!e) e = hipMemcpy((char *)d + b_atoms + b_start, pa->weight, (size_t)nw * sizeof(int),
+                          hipMemcpyHostToDevice);
+    if (e) {
+        hipFree(d);
+        return fail(DOCK_EDEVICE, std::string("pocket atom upload failed: ") + hipGetErrorString(e));
+    }
+    pk.release_atoms();
+    pk.d_contacts = d;
+    ContactArgs &ca = pk.ca;
+    ca.atoms = (const float4 *)d;
+    ca.cell_start = (const int *)((char *)d + b_atoms);
+    ca.weight = (const int *)((char *)d + b_atoms + b_start);
+    ca.ntypes = pa->ntypes;
+    ca.nw = nw;
+    ca.cx = (int)dims[0];
+    ca.cy = (int)dims[1];
+    ca.cz = (int)dims[2];
+    ca.lox = (float)lo[0];
+    ca.loy = (float)lo[1];
+    ca.loz = (float)lo[2];
+    ca.inv_cell = (float)(1.0 / h);
+    ca.dc2 = (float)((double)pa->contact_dist * (double)pa->contact_dist);
+    pk.has_atoms = true;
+    return DOCK_OK;
+}
+
 int dock_ligands_batch(dock_ctx *c, int32_t pocket, const dock_library *lib,
                        const dock_params *p, dock_results *o, void *stream) {
     if (!c) return fail(DOCK_EINVAL, "ctx is NULL");
@@ -1080,13 +1205,23 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
                 for (int per : {1, 2, 4, 0}) {
                     if (per >= occ) continue;  // same as 0 (all that fit)
                     const int blocks = (per > 0 ? per : occ) * c->num_cu;
-                    float t = 0.f;
-                    int e = timeit([&]() -> hipError_t {
-                        return launch_falign(bin, blocks, w, g, sa, la, wa, oa, -1, s);
-                    }, &t);
-                    if (e) return e;
-                    if (w == def.falign_waves && per == def.falign_per_cu) rep.falign_ms_default = t;
-                    if (t < best) { best = t; bs.falign_waves = w; bs.falign_per_cu = per; }
+                    for (int xg : {0, 1}) {
+                        float t = 0.f;
+                        int e = timeit([&]() -> hipError_t {
+                            return launch_falign(bin, blocks, w, g, sa, la, wa, oa, -1,
+                                                 xg ? kXcds : 0, s);
+                        }, &t);
+                        if (e) return e;
+                        if (w == def.falign_waves && per == def.falign_per_cu &&
+                            xg == def.falign_xcd)
+                            rep.falign_ms_default = t;
+                        if (t < best) {
+                            best = t;
+                            bs.falign_waves = w;
+                            bs.falign_per_cu = per;
+                            bs.falign_xcd = xg;
+                        }
+                    }
                 }
             }
             rep.falign_ms = best;
@@ -1094,6 +1229,7 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
             rep.select_waves = bs.select_waves;
             rep.falign_waves = bs.falign_waves;
             rep.falign_per_cu = bs.falign_per_cu;
+            rep.falign_xcd = bs.falign_xcd;
             if (out) out[bin] = rep;
         }
         c->tuned[tune_key(sa)] = pick;
@@ -1135,6 +1271,9 @@ int dock_set_tuning(dock_ctx *c, const dock_params *p, const dock_bin_tuning *ta
             if (t.falign_waves < 1 || t.falign_waves > 8)
                 return fail(DOCK_EINVAL, "falign_waves must be in [1,8]");
             if (t.falign_per_cu < 0) return fail(DOCK_EINVAL, "falign_per_cu must be >= 0");
+            if (t.falign_xcd != 0 && t.falign_xcd != 1)
+                return fail(DOCK_EINVAL, "falign_xcd must be 0 or 1");
+            b.falign_xcd = t.falign_xcd;
             b.dock_waves = t.dock_waves;
             b.select_waves = t.select_waves;
             b.falign_waves = t.falign_waves;
@@ -1264,6 +1403,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     dres.restart_score = o->restart_score ? (float *)(dr + t.o_rs) : nullptr;
     dres.trace = o->trace ? (uint16_t *)(dr + t.o_tr) : nullptr;
     dres.final_trace = o->final_trace ? (uint16_t *)(dr + t.o_ft) : nullptr;
+    dres.pose_contacts = o->pose_contacts ? (int32_t *)(dr + t.o_pc) : nullptr;
     int rc2 = enqueue_batch(c, it->second, &dl, p, &dres, s);
     if (rc2) {
         hipStreamSynchronize(s);
@@ -1323,6 +1463,7 @@ static int finish_ticket(dock_ctx *c, std::map<uint64_t, Ticket>::iterator it) {
         if (u.restart_score) std::memcpy(u.restart_score, h + t.o_rs, L * R * 4);
         if (u.trace) std::memcpy(u.trace, h + t.o_tr, (size_t)t.trace_len * 2);
         if (u.final_trace) std::memcpy(u.final_trace, h + t.o_ft, L * K * 2);
+        if (u.pose_contacts) std::memcpy(u.pose_contacts, h + t.o_pc, L * K * 4);
     }
     hipEventDestroy(t.done);
     hipHostFree(t.pinned);

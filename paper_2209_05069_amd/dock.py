@@ -54,13 +54,19 @@ class Params(ctypes.Structure):
 class Results(ctypes.Structure):
     _fields_ = [("best_score", P), ("n_poses", P), ("status", P), ("pose_score", P),
                 ("pose_restart", P), ("pose_xyz", P), ("restart_score", P), ("trace", P),
-                ("final_trace", P)]
+                ("final_trace", P), ("pose_contacts", P)]
+
+
+class PocketAtoms(ctypes.Structure):
+    _fields_ = [("n_atoms", ctypes.c_int32), ("ntypes", ctypes.c_int32),
+                ("contact_dist", ctypes.c_float), ("xyz", P), ("type", P), ("weight", P)]
 
 
 class BinTuning(ctypes.Structure):
     _fields_ = [("ligands", ctypes.c_int32), ("dock_waves", ctypes.c_int32),
                 ("select_waves", ctypes.c_int32), ("falign_waves", ctypes.c_int32),
-                ("falign_per_cu", ctypes.c_int32), ("dock_ms", ctypes.c_float),
+                ("falign_per_cu", ctypes.c_int32), ("falign_xcd", ctypes.c_int32),
+                ("dock_ms", ctypes.c_float),
                 ("select_ms", ctypes.c_float), ("falign_ms", ctypes.c_float),
                 ("dock_ms_default", ctypes.c_float), ("select_ms_default", ctypes.c_float),
                 ("falign_ms_default", ctypes.c_float)]
@@ -77,7 +83,8 @@ class Timing(ctypes.Structure):
 
 
 EXPORTS = ["dock_autotune", "dock_create", "dock_destroy", "dock_get_timing", "dock_last_error",
-           "dock_ligands_batch", "dock_ligands_batch_noalloc", "dock_pocket_load", "dock_pocket_unload", "dock_poll",
+           "dock_ligands_batch", "dock_ligands_batch_noalloc", "dock_pocket_load",
+           "dock_pocket_set_atoms", "dock_pocket_unload", "dock_poll",
            "dock_request_bytes", "dock_set_timing", "dock_set_tuning", "dock_submit", "dock_wait"]
 
 _lib = None
@@ -98,6 +105,7 @@ def lib():
         L.dock_last_error.restype = ctypes.c_char_p
         L.dock_pocket_load.argtypes = [P, ctypes.POINTER(GridDesc), ctypes.POINTER(ctypes.c_int32)]
         L.dock_pocket_unload.argtypes = [P, ctypes.c_int32]
+        L.dock_pocket_set_atoms.argtypes = [P, ctypes.c_int32, ctypes.POINTER(PocketAtoms)]
         L.dock_ligands_batch.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
                                          ctypes.POINTER(Params), ctypes.POINTER(Results), P]
         L.dock_ligands_batch_noalloc.argtypes = [P, ctypes.c_int32, ctypes.POINTER(Library),
@@ -151,6 +159,17 @@ def dock_pocket_load(ctx, values, spacing, origin) -> int:
 
 def dock_pocket_unload(ctx, pocket_id: int):
     _check(lib().dock_pocket_unload(ctx, pocket_id))
+
+
+def dock_pocket_set_atoms(ctx, pocket_id: int, xyz, types, ntypes: int, weight,
+                          contact_dist: float):
+    """Pocket atoms of the pairwise rescoring stand-in (see include/dock.h)."""
+    x = np.ascontiguousarray(xyz, np.float32).reshape(-1, 3)
+    t = np.ascontiguousarray(types, np.uint8)
+    w = np.ascontiguousarray(weight, np.int32)
+    pa = PocketAtoms(len(t), int(ntypes), float(contact_dist), _np_ptr(x), _np_ptr(t),
+                     ctypes.c_void_p(w.ctypes.data))
+    _check(lib().dock_pocket_set_atoms(ctx, pocket_id, ctypes.byref(pa)))
 
 
 DEFAULT_PARAMS = dict(torsion_steps=256, sweep_passes=3, align_steps=30, top_k=30, final_align=1,
@@ -239,7 +258,8 @@ class DeviceResults:
     """Device result buffers for a library and params (torch tensors)."""
 
     def __init__(self, n_ligands, n_atoms_total, n_rot_total, params: SearchParams,
-                 device="cuda:0", restart_scores=False, trace=False, final_trace=False):
+                 device="cuda:0", restart_scores=False, trace=False, final_trace=False,
+                 contacts=False):
         import torch
         L, K, R, Pp = n_ligands, params.top_k, params.restarts, params.sweep_passes
         self.L, self.K, self.R = L, K, R
@@ -254,15 +274,17 @@ class DeviceResults:
         self.trace = (torch.empty(R * (L + Pp * n_rot_total), dtype=i16, device=device)
                       if trace else None)
         self.final_trace = torch.empty(L * K, dtype=i16, device=device) if final_trace else None
+        self.pose_contacts = torch.empty(L * K, dtype=i32, device=device) if contacts else None
         self.s = Results(_t_ptr(self.best_score), _t_ptr(self.n_poses), _t_ptr(self.status),
                          _t_ptr(self.pose_score), _t_ptr(self.pose_restart), _t_ptr(self.pose_xyz),
-                         _t_ptr(self.restart_score), _t_ptr(self.trace), _t_ptr(self.final_trace))
+                         _t_ptr(self.restart_score), _t_ptr(self.trace), _t_ptr(self.final_trace),
+                         _t_ptr(self.pose_contacts))
 
     def to_host(self):
         """numpy copies of every buffer (traces as uint16)."""
         out = {}
         for k in ("best_score", "n_poses", "status", "pose_score", "pose_restart", "pose_xyz",
-                  "restart_score", "trace", "final_trace"):
+                  "restart_score", "trace", "final_trace", "pose_contacts"):
             t = getattr(self, k)
             if t is None:
                 out[k] = None
@@ -278,7 +300,7 @@ class HostResults:
     """Host (numpy) result buffers for dock_submit."""
 
     def __init__(self, n_ligands, n_atoms_total, n_rot_total, params: SearchParams,
-                 restart_scores=False, trace=False, final_trace=False):
+                 restart_scores=False, trace=False, final_trace=False, contacts=False):
         L, K, R, Pp = n_ligands, params.top_k, params.restarts, params.sweep_passes
         self.best_score = np.zeros(L, np.float32)
         self.n_poses = np.zeros(L, np.int32)
@@ -289,14 +311,15 @@ class HostResults:
         self.restart_score = np.zeros(L * R, np.float32) if restart_scores else None
         self.trace = np.zeros(R * (L + Pp * n_rot_total), np.uint16) if trace else None
         self.final_trace = np.zeros(L * K, np.uint16) if final_trace else None
+        self.pose_contacts = np.zeros(L * K, np.int32) if contacts else None
         self.s = Results(*[_np_ptr(getattr(self, k)) for k in (
             "best_score", "n_poses", "status", "pose_score", "pose_restart", "pose_xyz",
-            "restart_score", "trace", "final_trace")])
+            "restart_score", "trace", "final_trace", "pose_contacts")])
 
     def to_host(self):
         return {k: getattr(self, k) for k in ("best_score", "n_poses", "status", "pose_score",
                                                "pose_restart", "pose_xyz", "restart_score",
-                                               "trace", "final_trace")}
+                                               "trace", "final_trace", "pose_contacts")}
 
 
 def dock_ligands_batch(ctx, pocket: int, dlib: DeviceLibrary, params: SearchParams,
@@ -426,4 +449,6 @@ def ligand_outputs(h, l, atom_off, rot_off, params: SearchParams):
         out["trace"] = h["trace"][b:b + R * (1 + Pp * B)].reshape(R, 1 + Pp * B).copy()
     if h.get("final_trace") is not None:
         out["final_trace"] = h["final_trace"][l * K:l * K + npose].copy()
+    if h.get("pose_contacts") is not None:
+        out["pose_contacts"] = h["pose_contacts"][l * K:(l + 1) * K].copy()
     return out

@@ -53,7 +53,8 @@ def test_header_structs_match_binding_layout():
     src = open(HEADER).read()
     for struct, cls in (("dock_library", dock.Library), ("dock_params", dock.Params),
                         ("dock_results", dock.Results), ("dock_grid_desc", dock.GridDesc),
-                        ("dock_timing", dock.Timing), ("dock_bin_tuning", dock.BinTuning)):
+                        ("dock_timing", dock.Timing), ("dock_bin_tuning", dock.BinTuning),
+                        ("dock_pocket_atoms", dock.PocketAtoms)):
         body = re.search(r"typedef struct \{([^{}]*)\}\s*" + struct + ";", src).group(1)
         body = re.sub(r"/\*.*?\*/", "", body, flags=re.S)
         fields = []

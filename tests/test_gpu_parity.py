@@ -483,10 +483,12 @@ def test_autotune_reports_every_bin_and_keeps_results(D, ctx):
             continue
         assert t["dock_waves"] in (2, 4, 8) and t["select_waves"] in (4, 8, 16)
         assert t["falign_waves"] in (2, 4, 8) and t["falign_per_cu"] in (0, 1, 2, 4)
+        assert t["falign_xcd"] in (0, 1)
         for k in ("dock", "select", "falign"):
             assert 0 < t[f"{k}_ms"] <= t[f"{k}_ms_default"]
     h1 = run()
-    forced = [dict(t, dock_waves=8, select_waves=16, falign_waves=2, falign_per_cu=1)
+    forced = [dict(t, dock_waves=8, select_waves=16, falign_waves=2, falign_per_cu=1,
+                   falign_xcd=1 - t["falign_xcd"])
               if t["ligands"] else t for t in table]
     D.dock_set_tuning(ctx, params, forced)
     h2 = run()
@@ -495,3 +497,65 @@ def test_autotune_reports_every_bin_and_keeps_results(D, ctx):
         for k, a in h0.items():
             assert np.array_equal(a, h[k]), k
     D.dock_pocket_unload(ctx, pid)
+
+
+def _contacts_case(D, ctx, pk, lib, q, s, seed, label):
+    """Dock with contact scores in both forms; every output pose's GPU score must
+    equal the FP64 oracle's on the same pose, up to the weight of pairs within
+    1e-4 A of the contact distance; the forms and the submit path agree bitwise."""
+    pa = synth.pocket_atoms(seed, pk)
+    pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
+    D.dock_pocket_set_atoms(ctx, pid, pa.xyz, pa.type, pa.ntypes, pa.weight, pa.contact_dist)
+    dl = D.DeviceLibrary(lib)
+    outs = {}
+    for mode in (D.DOCK_MODE_BATCHED, D.DOCK_MODE_PLAIN):
+        params = D.SearchParams(q, mode=mode, **s)
+        res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params,
+                              contacts=True)
+        D.dock_ligands_batch(ctx, pid, dl, params, res)
+        torch.cuda.synchronize()
+        outs[mode] = res.to_host()
+    params = D.SearchParams(q, **s)
+    hr = D.HostResults(lib.n_ligands, int(lib.atom_off[-1]), int(lib.rot_off[-1]), params,
+                       contacts=True)
+    D.dock_wait(ctx, D.dock_submit(ctx, pid, lib, params, hr))
+    h = outs[D.DOCK_MODE_BATCHED]
+    for k in ("pose_contacts", "pose_xyz", "n_poses"):
+        assert np.array_equal(h[k], outs[D.DOCK_MODE_PLAIN][k]), k
+        assert np.array_equal(h[k], hr.to_host()[k]), k
+    opa = O.PocketAtoms.of(pa)
+    poses = exact = edge = 0
+    for l in range(lib.n_ligands):
+        g = D.ligand_outputs(h, l, lib.atom_off, lib.rot_off, params)
+        types = lib.type[lib.atom_off[l]:lib.atom_off[l + 1]]
+        assert (g["pose_contacts"][g["n_poses"]:] == 0).all()
+        for sidx in range(g["n_poses"]):
+            v, b = O.contacts(opa, types, g["pose_xyz"][sidx].astype(np.float64), tol=1e-4)
+            got = int(g["pose_contacts"][sidx])
+            assert abs(got - v) <= b, (l, sidx, got, v, b)
+            poses += 1
+            exact += got == v
+            edge += b > 0
+    print(f"[contacts {label}] poses {poses}, exact {exact}, with boundary pairs {edge}, "
+          f"{len(pa.type)} pocket atoms, nonzero {(h['pose_contacts'] != 0).sum()}", flush=True)
+    assert poses > 0 and (h["pose_contacts"] != 0).any()
+    D.dock_pocket_unload(ctx, pid)
+
+
+def test_pose_contacts_config1(D, ctx):
+    pk, lib, q, s = synth.config(1)
+    print("[case] contact rescoring, config 1", flush=True)
+    _contacts_case(D, ctx, pk, lib, q, s, 11, "c1")
+
+
+def test_pose_contacts_paper_scale_and_ragged(D, ctx):
+    pk, lib, q, s = synth.config(2, n_ligands=40)
+    print("[case] contact rescoring, paper-scale pocket, 40 ligands, restarts 0-31", flush=True)
+    _contacts_case(D, ctx, pk, lib, q[:32], dict(s, restarts=32), 12, "c2")
+    n = [1, 2, 20, 64, 65, 129, 200, 256]
+    b = [0, 0, 3, 8, 4, 10, 20, 30]
+    rl = synth.library_from_sizes(313, n, b)
+    rq = synth.start_quats(313, 6)
+    print("[case] contact rescoring, ragged sizes", flush=True)
+    _contacts_case(D, ctx, pk, rl, rq, dict(torsion_steps=32, sweep_passes=1, align_steps=7,
+                                            top_k=5, dedup_rmsd=1.0), 13, "ragged")
