@@ -60,6 +60,9 @@ def parse():
                     help="keep the default tiles (no per-bin autotuning before the timed steps)")
     ap.add_argument("--tune-ligands", type=int, default=4096,
                     help="ligands of the size-stratified sample the per-bin autotuner times on")
+    ap.add_argument("--bin-mode", type=int, default=0, choices=(0, 1),
+                    help="work lists of the batched form: 0 = size bins of 32 heavy atoms, "
+                         "1 = the paper's buckets (size bin x group of 4 rotatable bonds)")
     ap.add_argument("--no-prune", action="store_true",
                     help="the no-early-exit ablation: no bump-check pruning (bump_prune=0)")
     ap.add_argument("--serve", action="store_true",
@@ -415,7 +418,7 @@ def main():
     ctx = D.dock_create(0)
     pid = D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
     prune = 0 if a.no_prune else 1
-    params = D.SearchParams(q, bump_prune=prune, **s)
+    params = D.SearchParams(q, bump_prune=prune, bin_mode=a.bin_mode, **s)
     dl = D.DeviceLibrary(lib)
     res = D.DeviceResults(lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params)
     stream = torch.cuda.current_stream()
@@ -507,7 +510,9 @@ def main():
         "config": {
             "workload": describe(a.config, L, s) + ("; no bump-check pruning (ablation)"
                                                     if a.no_prune else ""),
-            "form": "batched (persistent wavefront-per-restart kernels, size-binned)",
+            "form": "batched (persistent wavefront-per-restart kernels, " +
+                    ("work lists per size bin x group of 4 rotatable bonds)" if a.bin_mode
+                     else "work lists per size bin)"),
             "ligands": L,
         },
         "torsion_evals_per_s": tors / (ms * 1e-3),

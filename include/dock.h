@@ -178,6 +178,11 @@ typedef struct {
                                   afterwards.  The selected steps are the same either
                                   way; 0 is the no-early-exit ablation of the paper's
                                   workload analysis (Execution Profiling). */
+    int32_t bin_mode;          /* batched form's work lists: 0 = one per size bin of 32
+                                  heavy atoms; 1 = the paper's buckets (Batched
+                                  Implementation): size bin x group of 4 rotatable
+                                  bonds (0-3, 4-7, ..., 28 and more), a launch per
+                                  bucket.  Results are the same either way. */
     float bump_dist;           /* Angstrom, >= 0 */
     float dedup_rmsd;          /* Angstrom, >= 0 (0: plain top-K) */
     const float *start_quat;   /* HOST [restarts][4] */
@@ -242,8 +247,8 @@ int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
  * tables (16*3R B of start rotations, 16*3A^2 B of alignment rotations, 8*T B
  * of torsion (cos, sin), 8*(A rounded up to 32) B of alignment (cos, sin)) plus
  * the workspace (per atom 32 B of bump-pair rows and 12*top_k B of kept poses;
- * per ligand 4*R B of restart scores, 32 B of bin lists and 12*top_k + 4 B of
- * selection records; 128 B of counters;
+ * per ligand 4*R B of restart scores, 32 B of work lists (256 B with bin_mode 1)
+ * and 12*top_k + 4 B of selection records; 1 KiB of counters;
  * and, when out->trace is NULL, 2*R*(L + P*n_rot_total) B of decision trace),
  * each part rounded up to a multiple of 256 B.
  * Every call on a device shares that device's array and leaves its contents

@@ -845,7 +845,7 @@ static __device__ __forceinline__ size_t trace_base(const LibArgs &lib, const Se
 // size bin; each wave docks one restart from the orientation k_align chose.
 template <int NS, int C>
 __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                              int bin) {
+                                              int bin, int lst) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -865,15 +865,15 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
         cs[c] = k < sa.T ? sa.tors[k] : make_float2(1.f, 0.f);
     }
     const int groups = (sa.R + W - 1) / W;
-    const long long total = (long long)ws.counters[bin] * groups;
+    const long long total = (long long)ws.counters[lst] * groups;
     int cur = -1;
     for (;;) {
-        if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[kNumBins + bin], 1);
+        if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[kMaxLists + lst], 1);
         __syncthreads();
         const int item = misc[0];
         if ((long long)item >= total) break;
         const int li = item / groups, grp = item - li * groups;
-        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        const int l = ws.bin_list[(size_t)lst * lib.L + li];
         if (l != cur) {
             stage_ligand<NS>(smem, nmax, l, lib, ws, g, true);
             cur = l;
@@ -1326,7 +1326,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
 // y rotations.  The last wave streams the next atom's band into LDS.
 template <int NS, int JM>
 __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                                int bin, int arena, int GR) {
+                                                int bin, int lst, int arena, int GR) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     const int BD = blockDim.x, W = BD >> 6, tid = threadIdx.x, wave = tid >> 6, lane = lane_id();
@@ -1342,19 +1342,19 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     const int region16 = (arena - (int)AlignLds::region(nmax, GR)) / 16;
     const Tri tr = make_tri(g);
     const int groups = (sa.R + GR - 1) / GR;
-    const long long total = (long long)ws.counters[bin] * groups;
+    const long long total = (long long)ws.counters[lst] * groups;
     const int Ws = W - 1;  // sampling waves; wave Ws copies bands
     const bool sampler = wave < Ws;
     // strips of one part padded to whole waves, so that j0 is wave-uniform
     const int spp = (GR * A + 63) & ~63, strips = parts * spp;
     if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     for (;;) {
-        if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kNumBins + bin], 1);
+        if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kMaxLists + lst], 1);
         __syncthreads();
         const int item = misc[0];
         if ((long long)item >= total) break;
         const int li = item / groups, grp = item - li * groups;
-        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        const int l = ws.bin_list[(size_t)lst * lib.L + li];
         const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
         const int B = lib.rot_off[l + 1] - lib.rot_off[l];
         const int rbase = grp * GR;
@@ -1666,7 +1666,7 @@ int select_sel_lds(int nmax, int waves, int R, int K) {
 
 template <int NS>
 __global__ __launch_bounds__(1024) void k_select(GridArgs g, SearchArgs sa, LibArgs lib,
-                                                WorkArgs ws, OutArgs out, int bin, int single,
+                                                WorkArgs ws, OutArgs out, int bin, int lst, int single,
                                                 int sel_lds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
@@ -1694,11 +1694,11 @@ __global__ __launch_bounds__(1024) void k_select(GridArgs g, SearchArgs sa, LibA
             if (pass > 0) break;
             l = single;
         } else {
-            if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[2 * kNumBins + bin], 1);
+            if (threadIdx.x == 0) misc[0] = atomicAdd(&ws.counters[2 * kMaxLists + lst], 1);
             __syncthreads();
             const int li = misc[0];
-            if (li >= ws.counters[bin]) break;
-            l = ws.bin_list[(size_t)bin * lib.L + li];
+            if (li >= ws.counters[lst]) break;
+            l = ws.bin_list[(size_t)lst * lib.L + li];
         }
         stage_ligand<NS>(smem, nmax, l, lib, ws, g, false);
         for (int r = threadIdx.x; r < R; r += blockDim.x) {
@@ -1895,7 +1895,7 @@ size_t falign_lds_bytes(int nmax, int waves, int single) {
 template <int NS>
 __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibArgs lib,
                                                WorkArgs ws, const int *__restrict__ status,
-                                               int bin, int single, int xcds) {
+                                               int bin, int lst, int single, int xcds) {
     extern __shared__ __align__(16) unsigned char smem[];
     const int nmax = bin_nmax(bin);
     // every lane is active here, so the wave index is read from the first lane
@@ -1919,7 +1919,7 @@ __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibAr
     // many XCDs (workgroup b on XCD b % xcds): XCD x takes a contiguous x-th share
     // of the bin's ligands, so the kept poses of a ligand share one L2.
     float4 *rec = (float4 *)(smem + (size_t)wave * nmax * 16);
-    const long long nl = ws.counters[bin];
+    const long long nl = ws.counters[lst];
     const int x = xcds > 1 ? (int)(blockIdx.x % xcds) : 0;
     const int bx = xcds > 1 ? (int)(blockIdx.x / xcds) : (int)blockIdx.x;
     const int nbx = xcds > 1 ? (int)((gridDim.x - x + xcds - 1) / xcds) : (int)gridDim.x;
@@ -1929,7 +1929,7 @@ __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibAr
     const long long nwaves = (long long)nbx * W;
     for (long long item = (long long)bx * W + wave; item < total; item += nwaves) {
         const int li = (int)(li0 + item / sa.K), s = (int)(item % sa.K);
-        const int l = ws.bin_list[(size_t)bin * lib.L + li];
+        const int l = ws.bin_list[(size_t)lst * lib.L + li];
         if (s < ws.nsel[l]) final_item<NS>(l, s, rec, tr, g, sa, lib, ws, WaveSplit(), true);
     }
 }
@@ -1940,7 +1940,7 @@ __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibAr
 // output slot.
 template <int NS>
 __global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArgs ws,
-                                             OutArgs out, int bin, int single) {
+                                             OutArgs out, int bin, int lst, int single) {
     __shared__ int rank[kMaxTopK];
     const int K = sa.K;
     const int W = blockDim.x >> 6, wave = threadIdx.x >> 6, lane = lane_id();
@@ -1950,8 +1950,8 @@ __global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArg
             if (li > 0 || out.status[single] != 0) break;
             l = single;
         } else {
-            if (li >= ws.counters[bin]) break;
-            l = ws.bin_list[(size_t)bin * lib.L + li];
+            if (li >= ws.counters[lst]) break;
+            l = ws.bin_list[(size_t)lst * lib.L + li];
         }
         const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
         const int ns = ws.nsel[l];
@@ -2226,9 +2226,13 @@ __global__ __launch_bounds__(64) void k_prep(GridArgs g, SearchArgs sa, LibArgs 
             }
         }
         if (lane == 0 && do_bin) {
+            // work list: the atom bin, or with sa.groups > 1 the paper's bucket of
+            // (atom bin, group of 4 rotatable bonds; the last group takes the rest)
             const int bin = (n - 1) >> 5;
-            const int pos = atomicAdd(&ws.counters[bin], 1);
-            ws.bin_list[(size_t)bin * lib.L + pos] = l;
+            const int grp = B / 4 < sa.groups - 1 ? B / 4 : sa.groups - 1;
+            const int lst = bin * sa.groups + grp;
+            const int pos = atomicAdd(&ws.counters[lst], 1);
+            ws.bin_list[(size_t)lst * lib.L + pos] = l;
         }
     } else {
         for (int s = lane; s < sa.K; s += 64) {
@@ -2252,10 +2256,10 @@ hipError_t launch_rescore(const ContactArgs &ca, const SearchArgs &sa, const Lib
     return hipGetLastError();
 }
 
-// Zero counters [first, first + count) (count <= 64): work-queue counters are
-// cleared by a kernel, not a memset, so the sequence can be captured in a graph.
+// Zero counters [first, first + count): work-queue counters are cleared by a
+// kernel, not a memset, so the sequence can be captured in a graph.
 __global__ void k_reset(int *counters, int first, int count) {
-    if ((int)threadIdx.x < count) counters[first + threadIdx.x] = 0;
+    for (int i = threadIdx.x; i < count; i += blockDim.x) counters[first + i] = 0;
 }
 
 // ---------------------------------------------------------------------------
@@ -2284,9 +2288,8 @@ hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blo
 }
 
 hipError_t launch_reset(int *counters, int first, int count, hipStream_t s) {
-    if (first < 0 || count < 0 || count > 64 || first + count > kNumCounters)
-        return hipErrorInvalidValue;
-    hipLaunchKernelGGL(k_reset, dim3(1), dim3(64), 0, s, counters, first, count);
+    if (first < 0 || count < 0 || first + count > kNumCounters) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(k_reset, dim3(1), dim3(256), 0, s, counters, first, count);
     return hipGetLastError();
 }
 
@@ -2339,40 +2342,41 @@ hipError_t launch_plain(int l, int bin, int waves, const GridArgs &g, const Sear
 }
 
 template <int NS, int C>
-static hipError_t launch_dock_t(int bin, int blocks, int waves, const GridArgs &g,
+static hipError_t launch_dock_t(int bin, int lst, int blocks, int waves, const GridArgs &g,
                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                 hipStream_t s) {
     const size_t lds = dock_lds_bytes(bin_nmax(bin), waves);
     hipFuncSetAttribute((const void *)k_dock<NS, C>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
-    hipLaunchKernelGGL((k_dock<NS, C>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, bin);
+    hipLaunchKernelGGL((k_dock<NS, C>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, bin,
+                       lst);
     return hipGetLastError();
 }
 
 template <int NS>
-static hipError_t launch_dock_c(int bin, int blocks, int waves, const GridArgs &g,
+static hipError_t launch_dock_c(int bin, int lst, int blocks, int waves, const GridArgs &g,
                                 const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                 hipStream_t s) {
     const int C = (sa.T + 63) / 64;
-    if (C <= 1) return launch_dock_t<NS, 1>(bin, blocks, waves, g, sa, lib, ws, s);
-    if (C <= 2) return launch_dock_t<NS, 2>(bin, blocks, waves, g, sa, lib, ws, s);
-    if (C <= 4) return launch_dock_t<NS, 4>(bin, blocks, waves, g, sa, lib, ws, s);
-    if (C <= 8) return launch_dock_t<NS, 8>(bin, blocks, waves, g, sa, lib, ws, s);
-    return launch_dock_t<NS, 16>(bin, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 1) return launch_dock_t<NS, 1>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 2) return launch_dock_t<NS, 2>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 4) return launch_dock_t<NS, 4>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+    if (C <= 8) return launch_dock_t<NS, 8>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+    return launch_dock_t<NS, 16>(bin, lst, blocks, waves, g, sa, lib, ws, s);
 }
 
-hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                       const LibArgs &lib, const WorkArgs &ws, hipStream_t s) {
+hipError_t launch_dock(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                       const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws, hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_dock_c<1>(bin, blocks, waves, g, sa, lib, ws, s);
-        case 2: return launch_dock_c<2>(bin, blocks, waves, g, sa, lib, ws, s);
-        case 3: return launch_dock_c<3>(bin, blocks, waves, g, sa, lib, ws, s);
-        default: return launch_dock_c<4>(bin, blocks, waves, g, sa, lib, ws, s);
+        case 1: return launch_dock_c<1>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+        case 2: return launch_dock_c<2>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+        case 3: return launch_dock_c<3>(bin, lst, blocks, waves, g, sa, lib, ws, s);
+        default: return launch_dock_c<4>(bin, lst, blocks, waves, g, sa, lib, ws, s);
     }
 }
 
 template <int NS>
-static hipError_t launch_select_t(int bin, int blocks, int waves, const GridArgs &g,
+static hipError_t launch_select_t(int bin, int lst, int blocks, int waves, const GridArgs &g,
                                   const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                   const OutArgs &out, int single, hipStream_t s) {
     const int sel = select_sel_lds(bin_nmax(bin), waves, sa.R, sa.K);
@@ -2380,52 +2384,55 @@ static hipError_t launch_select_t(int bin, int blocks, int waves, const GridArgs
     hipFuncSetAttribute((const void *)k_select<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     hipLaunchKernelGGL((k_select<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws, out,
-                       bin, single, sel);
+                       bin, lst, single, sel);
     return hipGetLastError();
 }
 
-hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         hipStream_t s) {
+hipError_t launch_select(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                         const OutArgs &out, int single, hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_select_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 2: return launch_select_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        case 3: return launch_select_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
-        default: return launch_select_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 1: return launch_select_t<1>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 2: return launch_select_t<2>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, s);
+        case 3: return launch_select_t<3>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, s);
+        default: return launch_select_t<4>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, s);
     }
 }
 
 template <int NS>
-static hipError_t launch_falign_t(int bin, int blocks, int waves, const GridArgs &g,
+static hipError_t launch_falign_t(int bin, int lst, int blocks, int waves, const GridArgs &g,
                                   const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                   const OutArgs &out, int single, int xcds, hipStream_t s) {
     const size_t lds = falign_lds_bytes(bin_nmax(bin), waves, single >= 0 ? 1 : 0);
     hipFuncSetAttribute((const void *)k_falign<NS>, hipFuncAttributeMaxDynamicSharedMemorySize,
                         (int)lds);
     hipLaunchKernelGGL((k_falign<NS>), dim3(blocks), dim3(64 * waves), lds, s, g, sa, lib, ws,
-                       (const int *)out.status, bin, single, xcds);
+                       (const int *)out.status, bin, lst, single, xcds);
     return hipGetLastError();
 }
 
-hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         int xcds, hipStream_t s) {
+hipError_t launch_falign(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                         const OutArgs &out, int single, int xcds, hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_falign_t<1>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
-        case 2: return launch_falign_t<2>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
-        case 3: return launch_falign_t<3>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
-        default: return launch_falign_t<4>(bin, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        case 1: return launch_falign_t<1>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        case 2: return launch_falign_t<2>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        case 3: return launch_falign_t<3>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
+        default: return launch_falign_t<4>(bin, lst, blocks, waves, g, sa, lib, ws, out, single, xcds, s);
     }
 }
 
-hipError_t launch_out(int bin, int blocks, const SearchArgs &sa, const LibArgs &lib,
+hipError_t launch_out(int bin, int lst, int blocks, const SearchArgs &sa, const LibArgs &lib,
                       const WorkArgs &ws, const OutArgs &out, int single, hipStream_t s) {
+#define DOCK_OUT_LAUNCH(NS) \
+    hipLaunchKernelGGL(k_out<NS>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, lst, single)
     switch (bin_slots(bin)) {
-        case 1: hipLaunchKernelGGL(k_out<1>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
-        case 2: hipLaunchKernelGGL(k_out<2>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
-        case 3: hipLaunchKernelGGL(k_out<3>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
-        default: hipLaunchKernelGGL(k_out<4>, dim3(blocks), dim3(256), 0, s, sa, lib, ws, out, bin, single); break;
+        case 1: DOCK_OUT_LAUNCH(1); break;
+        case 2: DOCK_OUT_LAUNCH(2); break;
+        case 3: DOCK_OUT_LAUNCH(3); break;
+        default: DOCK_OUT_LAUNCH(4); break;
     }
+#undef DOCK_OUT_LAUNCH
     return hipGetLastError();
 }
 
@@ -2454,24 +2461,24 @@ size_t align_lds_min(int bin, int A, int R) {
 }
 
 template <int NS>
-static hipError_t launch_align_t(int bin, int blocks, int arena, const GridArgs &g,
+static hipError_t launch_align_t(int bin, int lst, int blocks, int arena, const GridArgs &g,
                                  const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                                  hipStream_t s) {
     hipFuncSetAttribute((const void *)k_align<NS, kAlignJ>,
                         hipFuncAttributeMaxDynamicSharedMemorySize, arena);
     hipLaunchKernelGGL((k_align<NS, kAlignJ>), dim3(blocks), dim3(64 * align_waves(sa.A, sa.R)),
-                       (size_t)arena, s, g, sa, lib, ws, bin, arena, align_group(sa.A, sa.R));
+                       (size_t)arena, s, g, sa, lib, ws, bin, lst, arena, align_group(sa.A, sa.R));
     return hipGetLastError();
 }
 
-hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
+hipError_t launch_align(int bin, int lst, int blocks, int arena, const GridArgs &g,
                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                         hipStream_t s) {
     switch (bin_slots(bin)) {
-        case 1: return launch_align_t<1>(bin, blocks, arena, g, sa, lib, ws, s);
-        case 2: return launch_align_t<2>(bin, blocks, arena, g, sa, lib, ws, s);
-        case 3: return launch_align_t<3>(bin, blocks, arena, g, sa, lib, ws, s);
-        default: return launch_align_t<4>(bin, blocks, arena, g, sa, lib, ws, s);
+        case 1: return launch_align_t<1>(bin, lst, blocks, arena, g, sa, lib, ws, s);
+        case 2: return launch_align_t<2>(bin, lst, blocks, arena, g, sa, lib, ws, s);
+        case 3: return launch_align_t<3>(bin, lst, blocks, arena, g, sa, lib, ws, s);
+        default: return launch_align_t<4>(bin, lst, blocks, arena, g, sa, lib, ws, s);
     }
 }
 

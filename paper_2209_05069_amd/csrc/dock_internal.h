@@ -12,7 +12,9 @@ constexpr int kMaxTorsionSteps = 1024;  // matches DOCK_MAX_TORSION_STEPS
 constexpr int kNumBins = 8;         // bin b holds ligands with 32b < n <= 32(b+1)
 constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
-constexpr int kNumCounters = 4 * kNumBins;  // bin_count, dock_next, select_next, align_next
+constexpr int kMaxGroups = 8;       // paper buckets: rotatable bonds in groups of 4 (last: 28+)
+constexpr int kMaxLists = kNumBins * kMaxGroups;  // work lists (atom bin x bond group)
+constexpr int kNumCounters = 4 * kMaxLists;  // per list: count, dock_next, select_next, align_next
 constexpr int kMaxTopK = 64;        // matches DOCK_MAX_TOP_K
 constexpr int kXcds = 8;            // gfx950: workgroups go round-robin to 8 XCDs of 32 CUs
 constexpr int kAlignJ = 32;         // k_align: y rotations per lane
@@ -48,6 +50,7 @@ struct GridArgs {
 struct SearchArgs {
     int R, T, P, A, K, final_align, bmin;
     int prune;             // 1: prune the bump check and score only bump-free candidates
+    int groups;            // work lists per atom bin: 1, or kMaxGroups (paper buckets)
     float bump2g;          // (bump_dist / spacing)^2, grid units
     float dedup2;          // dedup_rmsd^2, Angstrom^2
     const float4 *smat;    // [R][3] start rotation rows (x,y,z,0)
@@ -71,8 +74,9 @@ struct LibArgs {
 
 struct WorkArgs {
     unsigned long long *far;  // [A_total][kFarWords]
-    int *counters;            // [kNumCounters]: bin_count, dock_next, select_next, align_next
-    int *bin_list;            // [kNumBins][L]
+    int *counters;            // [kNumCounters]: [4][kMaxLists] count, dock_next, select_next,
+                              // align_next of each work list
+    int *bin_list;            // [lists][L] ligands of each work list
     float *rscore;            // [L][R]
     uint16_t *rtrace;         // [R*(L + P*Nr_total)]
     float *acc_pose;          // [A_total*K*3] kept poses (aligned by the final step in place)
@@ -121,12 +125,14 @@ size_t falign_lds_bytes(int nmax, int waves, int single);
 // Launchers (return hipError_t of the launch).
 hipError_t launch_build_cubes(const float *values, float4 *cubes, int ntypes, int nx, int ny,
                               int nz, hipStream_t s);
-// Zero work-queue counters [first, first + count), count <= 64.
+// Zero work-queue counters [first, first + count), within [0, kNumCounters).
 hipError_t launch_reset(int *counters, int first, int count, hipStream_t s);
 hipError_t launch_prep(const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
                        const WorkArgs &ws, const OutArgs &out, hipStream_t s);
-hipError_t launch_dock(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                       const LibArgs &lib, const WorkArgs &ws, hipStream_t s);
+// Stage launches over work list `lst` of atom bin `bin` (lst = bin with one list
+// per bin, bin * kMaxGroups + group with the paper buckets).
+hipError_t launch_dock(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                       const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws, hipStream_t s);
 // Shell atlas of a pocket: pass 1 writes the geometry of kMaxBands bands into
 // info[2*kMaxBands]; pass 2 fills nb bands of every type.
 constexpr int kMaxBands = 240;
@@ -138,7 +144,7 @@ hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blo
                              int nb, hipStream_t s);
 // Batched alignment of a bin's ligands (k_align), `arena` bytes of LDS per
 // workgroup.
-hipError_t launch_align(int bin, int blocks, int arena, const GridArgs &g,
+hipError_t launch_align(int bin, int lst, int blocks, int arena, const GridArgs &g,
                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
                         hipStream_t s);
 // Smallest arena k_align accepts for the bin (fixed part plus a minimal region).
@@ -146,15 +152,15 @@ size_t align_lds_min(int bin, int A, int R);
 int align_blocks_per_cu(int bin, int R, int A, int arena);
 // Final stage of a bin.  single >= 0: only that ligand (plain form; k_falign then
 // runs one workgroup per kept pose), else the bin's queue.
-hipError_t launch_select(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         hipStream_t s);
+hipError_t launch_select(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                         const OutArgs &out, int single, hipStream_t s);
 // xcds > 1: the bin's ligands are split into that many contiguous shares, share x
 // taken by workgroups b with b % xcds == x (the XCD they are dispatched to).
-hipError_t launch_falign(int bin, int blocks, int waves, const GridArgs &g, const SearchArgs &sa,
-                         const LibArgs &lib, const WorkArgs &ws, const OutArgs &out, int single,
-                         int xcds, hipStream_t s);
-hipError_t launch_out(int bin, int blocks, const SearchArgs &sa, const LibArgs &lib,
+hipError_t launch_falign(int bin, int lst, int blocks, int waves, const GridArgs &g,
+                         const SearchArgs &sa, const LibArgs &lib, const WorkArgs &ws,
+                         const OutArgs &out, int single, int xcds, hipStream_t s);
+hipError_t launch_out(int bin, int lst, int blocks, const SearchArgs &sa, const LibArgs &lib,
                       const WorkArgs &ws, const OutArgs &out, int single, hipStream_t s);
 // Contact score (pairwise rescoring stand-in) of every output pose: single >= 0:
 // ligand `single` only, one workgroup per pose (grid top_k); else every ligand,

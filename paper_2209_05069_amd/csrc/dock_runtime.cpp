@@ -200,6 +200,7 @@ int check_params(const dock_params *p) {
     if (!(p->dedup_rmsd >= 0.f) || !std::isfinite(p->dedup_rmsd)) return fail(DOCK_EINVAL, "dedup_rmsd must be finite and >= 0");
     if (p->mode != DOCK_MODE_BATCHED && p->mode != DOCK_MODE_PLAIN) return fail(DOCK_EINVAL, "unknown mode");
     if (p->bump_prune != 0 && p->bump_prune != 1) return fail(DOCK_EINVAL, "bump_prune must be 0 or 1");
+    if (p->bin_mode != 0 && p->bin_mode != 1) return fail(DOCK_EINVAL, "bin_mode must be 0 or 1");
     if (!p->start_quat) return fail(DOCK_EINVAL, "start_quat is NULL");
     for (int r = 0; r < p->restarts; ++r) {
         double s = 0;
@@ -341,7 +342,8 @@ WsLayout ws_layout(const dock_library *lib, const dock_params *p, bool user_trac
     const size_t L = (size_t)lib->n_ligands, R = (size_t)p->restarts, K = (size_t)p->top_k;
     w.far = o; o += align256((size_t)lib->n_atoms_total * kFarWords * 8);
     w.counters = o; o += align256(kNumCounters * sizeof(int));
-    w.bin_list = o; o += align256((size_t)kNumBins * L * sizeof(int));
+    const size_t lists = (size_t)kNumBins * (p->bin_mode ? kMaxGroups : 1);
+    w.bin_list = o; o += align256(lists * L * sizeof(int));
     w.rscore = o; o += align256(L * R * sizeof(float));
     w.rtrace = o;
     if (!user_trace) o += align256(R * (L + (size_t)p->sweep_passes * lib->n_rot_total) * sizeof(uint16_t));
@@ -477,9 +479,9 @@ int enqueue_plain(dock_ctx *c, const dock_library *lib, const GridArgs &g, const
         if (n < 1 || n > kMaxAtoms) continue;  // flagged by the checks
         const int bin = (n - 1) >> 5;
         HIP_TRY(launch_plain(l, bin, kPlainWaves, g, sa, la, wa, oa, t));
-        HIP_TRY(launch_select(bin, 1, kPlainSelectWaves, g, sa, la, wa, oa, l, t));
-        HIP_TRY(launch_falign(bin, sa.K, kPlainFalignWaves, g, sa, la, wa, oa, l, 0, t));
-        HIP_TRY(launch_out(bin, 1, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_select(bin, bin, 1, kPlainSelectWaves, g, sa, la, wa, oa, l, t));
+        HIP_TRY(launch_falign(bin, bin, sa.K, kPlainFalignWaves, g, sa, la, wa, oa, l, 0, t));
+        HIP_TRY(launch_out(bin, bin, 1, sa, la, wa, oa, l, t));
         if (oa.pcontacts) HIP_TRY(launch_rescore(ca, sa, la, oa, l, 0, t));
     }
     for (size_t i = 0; i < c->plain_streams.size(); ++i) {
@@ -561,6 +563,7 @@ int prepare_launch(dock_ctx *c, const Pocket &pk, const dock_library *lib, const
     sa.final_align = p->final_align;
     sa.bmin = p->bump_min_bonds;
     sa.prune = p->bump_prune;
+    sa.groups = p->bin_mode ? kMaxGroups : 1;
     {
         const double bg = (double)p->bump_dist * (double)L->g.inv_h;
         sa.bump2g = (float)(bg * bg);
@@ -668,24 +671,34 @@ int run_sequence(dock_ctx *c, const Launch &L, const Shapes &sh, hipStream_t s,
     const LibArgs &la = L.la;
     const WorkArgs &wa = L.wa;
     const OutArgs &oa = L.oa;
+    const int G = sa.groups;
     HIP_TRY(launch_reset(wa.counters, 0, kNumCounters, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[0], s));
     HIP_TRY(launch_prep(g, sa, la, wa, oa, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[1], s));
+    // each stage: one launch per work list (atom bin, or atom bin x bond group)
     for (int bin = 0; bin < kNumBins; ++bin)
-        HIP_TRY(launch_align(bin, sh.align_blocks[bin], c->lds_arena, g, sa, la, wa, s));
+        for (int q = 0; q < G; ++q)
+            HIP_TRY(launch_align(bin, bin * G + q, sh.align_blocks[bin], c->lds_arena, g, sa, la,
+                                 wa, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[2], s));
     for (int bin = 0; bin < kNumBins; ++bin)
-        HIP_TRY(launch_dock(bin, sh.dock_blocks[bin], sh.tile[bin].dock_waves, g, sa, la, wa, s));
+        for (int q = 0; q < G; ++q)
+            HIP_TRY(launch_dock(bin, bin * G + q, sh.dock_blocks[bin], sh.tile[bin].dock_waves, g,
+                                sa, la, wa, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[3], s));
     for (int bin = 0; bin < kNumBins; ++bin)
-        HIP_TRY(launch_select(bin, sh.select_blocks[bin], sh.tile[bin].select_waves, g, sa, la, wa,
-                              oa, -1, s));
+        for (int q = 0; q < G; ++q)
+            HIP_TRY(launch_select(bin, bin * G + q, sh.select_blocks[bin],
+                                  sh.tile[bin].select_waves, g, sa, la, wa, oa, -1, s));
     for (int bin = 0; bin < kNumBins; ++bin)
-        HIP_TRY(launch_falign(bin, sh.falign_blocks[bin], sh.tile[bin].falign_waves, g, sa, la, wa,
-                              oa, -1, sh.tile[bin].falign_xcd ? kXcds : 0, s));
+        for (int q = 0; q < G; ++q)
+            HIP_TRY(launch_falign(bin, bin * G + q, sh.falign_blocks[bin],
+                                  sh.tile[bin].falign_waves, g, sa, la, wa, oa, -1,
+                                  sh.tile[bin].falign_xcd ? kXcds : 0, s));
     for (int bin = 0; bin < kNumBins; ++bin)
-        HIP_TRY(launch_out(bin, sh.out_blocks, sa, la, wa, oa, -1, s));
+        for (int q = 0; q < G; ++q)
+            HIP_TRY(launch_out(bin, bin * G + q, sh.out_blocks, sa, la, wa, oa, -1, s));
     if (oa.pcontacts) HIP_TRY(launch_rescore(L.ca, sa, la, oa, -1, sh.rescore_blocks, s));
     if (marks) HIP_TRY(hipEventRecord((*marks)[4], s));
     return DOCK_OK;
@@ -1136,9 +1149,11 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
         // one whole pass fills the workspace the stage kernels read
         rc2 = run_sequence(c, Lc, sh, s, nullptr);
         if (rc2) return rc2;
-        int counts[kNumBins];
-        HIP_TRY(hipMemcpyAsync(counts, Lc.wa.counters, sizeof(counts), hipMemcpyDeviceToHost, s));
+        int lcount[kMaxLists], counts[kNumBins] = {};
+        HIP_TRY(hipMemcpyAsync(lcount, Lc.wa.counters, sizeof(lcount), hipMemcpyDeviceToHost, s));
         HIP_TRY(hipStreamSynchronize(s));
+        const int G = Lc.sa.groups;
+        for (int q = 0; q < kNumBins * G; ++q) counts[q / G] += lcount[q];
         const GridArgs &g = Lc.g;
         const SearchArgs &sa = Lc.sa;
         const LibArgs &la = Lc.la;
@@ -1175,8 +1190,10 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
                 const int blocks = dock_blocks_per_cu(bin, w, sa.T) * c->num_cu;
                 float t = 0.f;
                 int e = timeit([&]() -> hipError_t {
-                    hipError_t q = launch_reset(wa.counters, kNumBins + bin, 1, s);
-                    return q ? q : launch_dock(bin, blocks, w, g, sa, la, wa, s);
+                    hipError_t q = launch_reset(wa.counters, kMaxLists + bin * G, G, s);
+                    for (int k = 0; k < G && !q; ++k)
+                        q = launch_dock(bin, bin * G + k, blocks, w, g, sa, la, wa, s);
+                    return q;
                 }, &t);
                 if (e) return e;
                 if (w == def.dock_waves) rep.dock_ms_default = t;
@@ -1190,8 +1207,10 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
                 blocks = blocks > la.L ? la.L : blocks;
                 float t = 0.f;
                 int e = timeit([&]() -> hipError_t {
-                    hipError_t q = launch_reset(wa.counters, 2 * kNumBins + bin, 1, s);
-                    return q ? q : launch_select(bin, blocks, w, g, sa, la, wa, oa, -1, s);
+                    hipError_t q = launch_reset(wa.counters, 2 * kMaxLists + bin * G, G, s);
+                    for (int k = 0; k < G && !q; ++k)
+                        q = launch_select(bin, bin * G + k, blocks, w, g, sa, la, wa, oa, -1, s);
+                    return q;
                 }, &t);
                 if (e) return e;
                 if (w == def.select_waves) rep.select_ms_default = t;
@@ -1208,8 +1227,11 @@ int dock_autotune(dock_ctx *c, int32_t pocket, const dock_library *lib, const do
                     for (int xg : {0, 1}) {
                         float t = 0.f;
                         int e = timeit([&]() -> hipError_t {
-                            return launch_falign(bin, blocks, w, g, sa, la, wa, oa, -1,
-                                                 xg ? kXcds : 0, s);
+                            hipError_t q = hipSuccess;
+                            for (int k = 0; k < G && !q; ++k)
+                                q = launch_falign(bin, bin * G + k, blocks, w, g, sa, la, wa, oa,
+                                                  -1, xg ? kXcds : 0, s);
+                            return q;
                         }, &t);
                         if (e) return e;
                         if (w == def.falign_waves && per == def.falign_per_cu &&

@@ -47,7 +47,8 @@ class Params(ctypes.Structure):
                 ("sweep_passes", ctypes.c_int32), ("align_steps", ctypes.c_int32),
                 ("top_k", ctypes.c_int32), ("final_align", ctypes.c_int32),
                 ("bump_min_bonds", ctypes.c_int32), ("mode", ctypes.c_int32),
-                ("bump_prune", ctypes.c_int32), ("bump_dist", ctypes.c_float),
+                ("bump_prune", ctypes.c_int32), ("bin_mode", ctypes.c_int32),
+                ("bump_dist", ctypes.c_float),
                 ("dedup_rmsd", ctypes.c_float), ("start_quat", P)]
 
 
@@ -174,7 +175,7 @@ def dock_pocket_set_atoms(ctx, pocket_id: int, xyz, types, ntypes: int, weight,
 
 DEFAULT_PARAMS = dict(torsion_steps=256, sweep_passes=3, align_steps=30, top_k=30, final_align=1,
                       bump_min_bonds=4, bump_dist=2.0, dedup_rmsd=2.0, mode=DOCK_MODE_BATCHED,
-                      bump_prune=1)
+                      bump_prune=1, bin_mode=0)
 
 
 class SearchParams:
@@ -193,7 +194,7 @@ class SearchParams:
         self.values = p
         self.s = Params(len(self.quat), p["torsion_steps"], p["sweep_passes"], p["align_steps"],
                         p["top_k"], p["final_align"], p["bump_min_bonds"], p["mode"],
-                        p["bump_prune"], p["bump_dist"], p["dedup_rmsd"],
+                        p["bump_prune"], p["bin_mode"], p["bump_dist"], p["dedup_rmsd"],
                         ctypes.c_void_p(self.quat.ctypes.data))
 
     def __getattr__(self, k):
