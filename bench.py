@@ -38,7 +38,19 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # one wave64 FMA per CU per clock (packed FP3
 # read in the same program).  Valid only for the kernel source they were taken
 # on (sha256 prefix) and the workload they were taken on: reported as null
 # otherwise.  Key: (config, torsion steps, ligands) -> (kernel, source sha, bytes).
-TRAFFIC = {}
+TRAFFIC = {
+    # large batched workload, T=256: rocprofv3 FETCH_SIZE / WRITE_SIZE of k_align (all bins),
+    # one step, scaled by the 256 MiB reference copy (factors 2.0 and 1.0)
+    (3, 256, 200000): ("k_align", "a81209f523c14b41", 3.4858e12),
+}
+
+# VALU wave-instructions per step of all docking kernels (rocprofv3 SQ_INSTS_VALU, one
+# step), for the VALU-instruction roofline: one wave64 VALU instruction per CU per
+# clock, 256 CUs at 2.4 GHz.  Same validity rule as TRAFFIC: (source sha, instructions).
+VALU_INSTR = {
+    (3, 256, 200000): ("a81209f523c14b41", 3.3049e12),
+}
+VALU_ROOF_PER_S = 256 * 2.4e9
 
 
 def parse():
@@ -58,6 +70,12 @@ def parse():
                          "latency (0: skip)")
     ap.add_argument("--no-tune", action="store_true",
                     help="keep the default tiles (no per-bin autotuning before the timed steps)")
+    ap.add_argument("--save-tuning", type=str, default=None,
+                    help="write the autotuned table (with device and search settings) to this "
+                         "JSON file")
+    ap.add_argument("--tuning-file", type=str, default=None,
+                    help="use the table in this JSON file (written by --save-tuning on the same "
+                         "device and search settings) instead of autotuning")
     ap.add_argument("--tune-ligands", type=int, default=4096,
                     help="ligands of the size-stratified sample the per-bin autotuner times on")
     ap.add_argument("--bin-mode", type=int, default=0, choices=(0, 1),
@@ -100,6 +118,17 @@ def kernel_traffic(cfg, L, s, kernel):
             or s != synth.CONFIGS[cfg]["search"] or L != synth.CONFIGS[cfg]["ligands"]["L"]):
         return None
     return t[2]
+
+
+def step_valu_instr(cfg, L, s):
+    """Measured VALU wave-instructions per step, or None unless they were taken on
+    this kernel source, this workload recipe, its full library and its search."""
+    import synth
+    t = VALU_INSTR.get((cfg, s["torsion_steps"], L))
+    if (t is None or t[0] != source_sha() or s != synth.CONFIGS[cfg]["search"]
+            or L != synth.CONFIGS[cfg]["ligands"]["L"]):
+        return None
+    return t[1]
 
 
 def stratified_order(lib, seed):
@@ -431,7 +460,19 @@ def main():
         del src, dst
     order = stratified_order(lib, 2209)
     tuning = None
-    if not a.no_tune:
+    tune_key = {"device": torch.cuda.get_device_properties(0).gcnArchName.split(":")[0],
+                "search": {k: s[k] for k in ("restarts", "torsion_steps", "align_steps", "top_k",
+                                             "sweep_passes")}}
+    if a.tuning_file:
+        saved = json.load(open(a.tuning_file))
+        if {k: saved.get(k) for k in tune_key} != tune_key:
+            raise SystemExit(f"{a.tuning_file} was tuned for {saved.get('device')} "
+                             f"{saved.get('search')}, not {tune_key}")
+        D.dock_set_tuning(ctx, params, saved["table"])
+        tuning = {"from_file": a.tuning_file,
+                  "bins": {f"atoms {32 * b + 1}-{32 * (b + 1)}": t
+                           for b, t in enumerate(saved["table"]) if t["ligands"] > 0}}
+    elif not a.no_tune:
         t1 = time.time()
         tsub = lib.subset(sorted(order[:min(a.tune_ligands, lib.n_ligands)]))
         table = D.dock_autotune(ctx, pid, D.DeviceLibrary(tsub), params, stream)
@@ -441,6 +482,9 @@ def main():
                            for b, t in enumerate(table) if t["ligands"] > 0}}
         print(f"[bench] autotuned in {tuning['seconds']:.1f}s: {tuning['bins']}",
               file=sys.stderr, flush=True)
+        if a.save_tuning:
+            with open(a.save_tuning, "w") as f:
+                json.dump(dict(tune_key, table=table), f)
     for w in range(a.warmup):
         D.dock_ligands_batch(ctx, pid, dl, params, res, stream)
         torch.cuda.synchronize()
@@ -537,6 +581,13 @@ def main():
             "kernels": kernels,
         },
     }
+    vi = step_valu_instr(a.config, L, s) if not (a.no_prune or a.bin_mode) else None
+    out["valu_roofline"] = None if vi is None else {
+        "wave_instr_per_step": vi, "achieved_per_s": vi / (ms * 1e-3),
+        "peak_per_s": VALU_ROOF_PER_S, "frac": vi / (ms * 1e-3) / VALU_ROOF_PER_S,
+        "note": "VALU wave-instructions of every docking kernel per step (rocprofv3 "
+                "SQ_INSTS_VALU on this kernel source and workload) over the live step time; "
+                "roof = one wave64 VALU instruction per CU per clock (256 CUs, 2.4 GHz)"}
     out["tuning"] = tuning if tuning is not None else "default tiles (--no-tune)"
     if a.plain_ligands > 0:
         pf = plain_form(D, torch, ctx, pid, lib, q, dict(s, bump_prune=prune), order,

@@ -73,3 +73,20 @@ def test_more_than_one_gpu_is_refused():
                        capture_output=True, text=True, timeout=120)
     assert r.returncode == 2
     assert "one GPU" in r.stderr
+
+
+def test_valu_instructions_only_for_the_measured_source_and_workload():
+    s3 = dict(synth.CONFIGS[3]["search"])
+    L3 = synth.CONFIGS[3]["ligands"]["L"]
+    saved = dict(bench.VALU_INSTR)
+    try:
+        bench.VALU_INSTR.clear()
+        bench.VALU_INSTR[(3, 256, L3)] = (_source_sha(), 2.0e12)
+        assert bench.step_valu_instr(3, L3, s3) == 2.0e12
+        assert bench.step_valu_instr(3, L3, dict(s3, restarts=128)) is None
+        assert bench.step_valu_instr(3, L3 - 1, s3) is None
+        bench.VALU_INSTR[(3, 256, L3)] = ("0" * 16, 2.0e12)
+        assert bench.step_valu_instr(3, L3, s3) is None
+    finally:
+        bench.VALU_INSTR.clear()
+        bench.VALU_INSTR.update(saved)
