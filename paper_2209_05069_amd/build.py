@@ -15,6 +15,9 @@ def build(verbose: bool = False) -> str:
     tmp = LIB + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-shared",
            "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops", "-Wno-unused-value",
+           # contraction of a*b+c only within one source expression: the same helper
+           # then rounds the same way wherever it is inlined (bitwise-equal forms)
+           "-ffp-contract=on",
            "-x", "hip", SOURCES[0], "-x", "hip", SOURCES[1],
            "-I", os.path.join(ROOT, "include"), "-I", os.path.join(HERE, "csrc"),
            "-o", tmp]

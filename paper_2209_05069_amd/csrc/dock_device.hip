@@ -1888,8 +1888,156 @@ __device__ void final_item(int l, int s, float4 *rec, const Tri &tr, const GridA
     }
 }
 
+// Final step of kept poses s0 and s0 + 1 (when s0 + 1 < ns) of ligand l in one
+// wave, for A <= 32 with final_align: lane (h, i) = (lane / 32, lane % 32) holds
+// the strip of pose h, x rotation i and the A y rotations, one accumulator each.
+// Per atom the x rotation is applied once (align_x) and each y rotation costs 4
+// FMAs, and the cube loads of kFalignBatch samples are issued before the first
+// blend waits for them.  Every sample, the atom-order sums and the tie rule
+// (first maximum in o = i*A + j) are those of align_pose, and the chosen
+// orientation is applied and scored as there, so fscore / fo are bit-identical
+// to final_item's.  rec: LDS for 2 * nmax float4.
+constexpr int kFalignBatch = 4;
+
+template <int NS>
+__device__ void final_pair(int l, int s0, int ns, float4 *rec, int nmax, const Tri &tr,
+                           const GridArgs &g, const SearchArgs &sa, const LibArgs &lib,
+                           const WorkArgs &ws) {
+    const int lane = lane_id(), h = lane >> 5, i = lane & 31;
+    const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0, K = sa.K, A = sa.A;
+    const int np = s0 + 1 < ns ? 2 : 1;
+    int toff[NS];
+#pragma unroll
+    for (int q = 0; q < NS; ++q) {
+        const int ia = lane + 64 * q;
+        toff[q] = ia < n ? (int)((uint32_t)lib.type[a0 + ia] * g.type_bytes) : 0;
+    }
+    // records of both poses: centred grid-unit offsets and type offsets, as in
+    // align_pose; every sample inside the grid unless some atom's sphere may leave it
+    float ex[2] = {0.f, 0.f}, ey[2] = {0.f, 0.f}, ez[2] = {0.f, 0.f};
+    bool out_any = false;
+    for (int p = 0; p < np; ++p) {
+        const float *P = ws.acc_pose + ((size_t)a0 * K + (size_t)(s0 + p) * n) * 3;
+        Pose<NS> Y;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int ia = lane + 64 * q, ii = ia < n ? ia : 0;
+            Y.x[q] = P[3 * ii + 0];
+            Y.y[q] = P[3 * ii + 1];
+            Y.z[q] = P[3 * ii + 2];
+        }
+        float cx, cy, cz;
+        centroid(Y, n, cx, cy, cz);
+        ex[p] = (cx - g.ox) * g.inv_h;
+        ey[p] = (cy - g.oy) * g.inv_h;
+        ez[p] = (cz - g.oz) * g.inv_h;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int ia = lane + 64 * q;
+            if (ia < n) {
+                const float rx = (Y.x[q] - cx) * g.inv_h, ry = (Y.y[q] - cy) * g.inv_h,
+                            rz = (Y.z[q] - cz) * g.inv_h;
+                out_any = out_any || !ball_inside(tr, ex[p], ey[p], ez[p],
+                                                  ball_radius(fmaf(rx, rx, fmaf(ry, ry, rz * rz))));
+                rec[p * nmax + ia] = make_float4(rx, ry, rz, __int_as_float(toff[q]));
+            }
+        }
+    }
+    const bool all_in = __ballot(out_any) == 0ull;
+    wave_lds_sync();
+    // strips; lanes without one (i >= A, or the second pose missing) mirror a valid
+    // strip so that their reads stay in range, and take no part in the maximum
+    const bool valid = h < np && i < A;
+    const int hp = h < np ? h : 0;
+    const float pex = hp ? ex[1] : ex[0], pey = hp ? ey[1] : ey[0], pez = hp ? ez[1] : ez[0];
+    const float2 ci = sa.acs[i < A ? i : 0];
+    const cfloat2_p cj = (cfloat2_p)sa.acs;  // padded to 32 entries (k >= A wraps)
+    const float4 *rp = rec + hp * nmax;
+    float acc[32];
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) acc[jj] = 0.0f;
+    for (int a = 0; a < n; ++a) {
+        const float4 r = rp[a];
+        const int to = uniform_int(__float_as_int(rec[a].w));  // same atom, same type in both
+        const XStage xs = align_x(r.x, r.y, r.z, ci, pey);
+#pragma unroll
+        for (int j0 = 0; j0 < 32; j0 += kFalignBatch) {
+            if (j0 < A) {
+                float fx[kFalignBatch], fy[kFalignBatch], fz[kFalignBatch];
+                uint32_t off[kFalignBatch];
+#pragma unroll
+                for (int k = 0; k < kFalignBatch; ++k) {
+                    const float2 c = ld_cs(cj, j0 + k);
+                    const float gx = align_gx(xs, c, pex), gz = align_gz(xs, c, pez);
+                    if (all_in) {
+                        // tri_in's cell and fractions
+                        fx[k] = __builtin_amdgcn_fractf(gx);
+                        fy[k] = __builtin_amdgcn_fractf(xs.gy);
+                        fz[k] = __builtin_amdgcn_fractf(gz);
+                        off[k] = in_cell(tr, gx, xs.gy, gz);
+                    } else {
+                        // tri_u's clamped cell and fractions
+                        off[k] = tri_cell(tr, gx, xs.gy, gz, fx[k], fy[k], fz[k]);
+                    }
+                }
+                float4 q0[kFalignBatch], q1[kFalignBatch];
+#pragma unroll
+                for (int k = 0; k < kFalignBatch; ++k) {
+                    q0[k] = ldq(tr.rs, off[k], to);
+                    q1[k] = ldq(tr.rs, off[k], to + 16);
+                }
+                // every load of the batch is issued before the first blend waits
+                __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+                for (int k = 0; k < kFalignBatch; ++k)
+                    acc[j0 + k] += tri_blend(q0[k], q1[k], fx[k], fy[k], fz[k]);
+            }
+            __builtin_amdgcn_sched_barrier(0);
+        }
+    }
+    // best (score, then lowest index) of each pose: lane maxima, then a max over
+    // each half wave (rows 0-1 into lane 31, rows 2-3 into lane 63)
+    u64 best = 0ull;
+#pragma unroll
+    for (int jj = 0; jj < 32; ++jj) {
+        const u64 key = valid && jj < A ? make_key(acc[jj], (uint32_t)(i * A + jj)) : 0ull;
+        best = key > best ? key : best;
+    }
+#define DOCK_HALF_MAX_STEP(C, R)            \
+    {                                       \
+        const u64 w = dpp_read64<C, R>(best); \
+        best = w > best ? w : best;         \
+    }
+    DOCK_HALF_MAX_STEP(0x111, 0xF)
+    DOCK_HALF_MAX_STEP(0x112, 0xF)
+    DOCK_HALF_MAX_STEP(0x114, 0xF)
+    DOCK_HALF_MAX_STEP(0x118, 0xF)
+    DOCK_HALF_MAX_STEP(0x142, 0xA)
+#undef DOCK_HALF_MAX_STEP
+    const u64 bk[2] = {read_lane64(best, 31), read_lane64(best, 63)};
+    wave_lds_sync();  // rec is rewritten by the wave's next item
+    for (int p = 0; p < np; ++p) {
+        const int ob = (int)key_index(bk[p]);
+        const float *P = ws.acc_pose + ((size_t)a0 * K + (size_t)(s0 + p) * n) * 3;
+        Pose<NS> Y;
+#pragma unroll
+        for (int q = 0; q < NS; ++q) {
+            const int ia = lane + 64 * q, ii = ia < n ? ia : 0;
+            Y.x[q] = P[3 * ii + 0];
+            Y.y[q] = P[3 * ii + 1];
+            Y.z[q] = P[3 * ii + 2];
+        }
+        apply_align(Y, n, ob, sa);
+        const float sc = pose_score(Y, n, toff, tr, g);
+        if (lane == 0) {
+            ws.fscore[(size_t)l * K + s0 + p] = sc;
+            ws.fo[(size_t)l * K + s0 + p] = ob;
+        }
+    }
+}
+
 size_t falign_lds_bytes(int nmax, int waves, int single) {
-    return single ? (size_t)nmax * 16 + (size_t)waves * 8 : (size_t)waves * nmax * 16;
+    return single ? (size_t)nmax * 16 + (size_t)waves * 8 : (size_t)waves * 2 * nmax * 16;
 }
 
 template <int NS>
@@ -1918,19 +2066,29 @@ __global__ __launch_bounds__(512) void k_falign(GridArgs g, SearchArgs sa, LibAr
     // With xcds > 1 the workgroups are taken as dispatched round-robin over that
     // many XCDs (workgroup b on XCD b % xcds): XCD x takes a contiguous x-th share
     // of the bin's ligands, so the kept poses of a ligand share one L2.
-    float4 *rec = (float4 *)(smem + (size_t)wave * nmax * 16);
+    // An item is a pair of kept poses (s0 = 2 * pair, s0 + 1) of one ligand.
+    float4 *rec = (float4 *)(smem + (size_t)wave * 2 * nmax * 16);
     const long long nl = ws.counters[lst];
     const int x = xcds > 1 ? (int)(blockIdx.x % xcds) : 0;
     const int bx = xcds > 1 ? (int)(blockIdx.x / xcds) : (int)blockIdx.x;
     const int nbx = xcds > 1 ? (int)((gridDim.x - x + xcds - 1) / xcds) : (int)gridDim.x;
     const int nx = xcds > 1 ? xcds : 1;
+    const int pairs = (sa.K + 1) / 2;
+    const bool strips = sa.final_align && sa.A <= 32;
     const long long li0 = nl * x / nx, li1 = nl * (x + 1) / nx;
-    const long long total = (li1 - li0) * sa.K;
+    const long long total = (li1 - li0) * pairs;
     const long long nwaves = (long long)nbx * W;
     for (long long item = (long long)bx * W + wave; item < total; item += nwaves) {
-        const int li = (int)(li0 + item / sa.K), s = (int)(item % sa.K);
+        const int li = (int)(li0 + item / pairs), s0 = 2 * (int)(item % pairs);
         const int l = ws.bin_list[(size_t)lst * lib.L + li];
-        if (s < ws.nsel[l]) final_item<NS>(l, s, rec, tr, g, sa, lib, ws, WaveSplit(), true);
+        const int ns = ws.nsel[l];
+        if (s0 >= ns) continue;
+        if (strips) {
+            final_pair<NS>(l, s0, ns, rec, nmax, tr, g, sa, lib, ws);
+        } else {
+            final_item<NS>(l, s0, rec, tr, g, sa, lib, ws, WaveSplit(), true);
+            if (s0 + 1 < ns) final_item<NS>(l, s0 + 1, rec, tr, g, sa, lib, ws, WaveSplit(), true);
+        }
     }
 }
 
