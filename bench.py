@@ -86,8 +86,13 @@ def parse():
     ap.add_argument("--serve", action="store_true",
                     help="run the serving workload (8 pockets, Poisson requests) instead")
     ap.add_argument("--serve-seconds", type=float, default=8.0)
-    ap.add_argument("--serve-loads", type=str, default="0.5,0.8",
+    ap.add_argument("--serve-loads", type=str, default="0.5,0.8,0.9",
                     help="offered load as fractions of the measured batched saturation")
+    ap.add_argument("--serve-max-inflight", type=int, default=4,
+                    help="serving: batches in flight at most (work-conserving policy); 0 = "
+                         "submit a pocket's bucket when full or after --serve-flush-ms")
+    ap.add_argument("--serve-max-batch", type=int, default=4096)
+    ap.add_argument("--serve-flush-ms", type=float, default=50.0)
     ap.add_argument("--sweep", action="store_true",
                     help="size grid and library-size sweep, plain vs batched (config 4)")
     ap.add_argument("--sweep-ligands", type=int, default=20000,
@@ -255,9 +260,10 @@ def serve_main(a):
     pids = {p: D.dock_pocket_load(ctx, pk.values, pk.spacing, pk.origin)
             for p, pk in enumerate(pockets)}
     params = D.SearchParams(q, **s)
-    # saturation on this mix: one big device-resident batch
+    # saturation on this mix: one big device-resident batch (tiles tuned on it first)
     sat_lib = synth.library_lognormal(seed, 6000)
     dl = D.DeviceLibrary(sat_lib)
+    tuning = D.dock_autotune(ctx, pids[0], dl, params)
     res = D.DeviceResults(sat_lib.n_ligands, dl.n_atoms_total, dl.n_rot_total, params)
     D.dock_ligands_batch(ctx, pids[0], dl, params, res)
     torch.cuda.synchronize()
@@ -277,7 +283,8 @@ def serve_main(a):
         rng = np.random.default_rng(seed + int(1000 * load))
         reqs = [S.Request(i, int(rng.integers(0, 8)), i, 0.0) for i in range(n)]
         arr = S.poisson_arrivals(qps, n, seed + int(1000 * load))
-        srv = S.Server(ctx, pids, lib, params, max_batch=2048, flush_ms=50.0)
+        srv = S.Server(ctx, pids, lib, params, max_batch=a.serve_max_batch,
+                       flush_ms=a.serve_flush_ms, max_inflight=a.serve_max_inflight)
         r = S.run(srv, reqs, arr)
         r.update(load=load, offered_qps=qps)
         runs.append(r)
@@ -291,8 +298,13 @@ def serve_main(a):
         "config": {"workload": "serving: 8 device-resident 4x96^3 pockets, Poisson requests "
                                "(one ligand each, pocket U{0..7}), heavy atoms lognormal(40, 0.5) "
                                "clipped 12..150, rotatable bonds Poisson(6) clipped 0..30, "
-                               "R=T=256, P=3, K=30; buckets per pocket, flush at 2048 ligands or "
-                               "50 ms"},
+                               "R=T=256, P=3, K=30; buckets per pocket; " +
+                               (f"work-conserving: at most {a.serve_max_inflight} batches in "
+                                f"flight, oldest bucket first, up to {a.serve_max_batch} ligands"
+                                if a.serve_max_inflight > 0 else
+                                f"flush at {a.serve_max_batch} ligands or {a.serve_flush_ms} ms")},
+        "tuning": {f"atoms {32 * b + 1}-{32 * (b + 1)}": t for b, t in enumerate(tuning)
+                   if t["ligands"] > 0},
         "latency_ms": {"p50": main_run["p50_ms"], "p99": main_run["p99_ms"]},
         "batched_saturation_ligands_per_s": sat,
         "runs": runs,

@@ -190,8 +190,10 @@ typedef struct {
 
 /* Outputs.  Same memory kind as the library (device for dock_ligands_batch,
  * host for dock_submit).  Required: best_score, n_poses, status, pose_score,
- * pose_restart, pose_xyz.  Optional (NULL to skip): restart_score, trace,
- * final_trace.
+ * pose_restart.  Optional (NULL to skip): pose_xyz (required with
+ * pose_contacts), restart_score, trace, final_trace, pose_contacts.  Skipping
+ * pose_xyz changes nothing else (a screening service that keeps only scores
+ * saves its A*K*12 bytes of transfer per request).
  *   pose_score[l*K + s], pose_restart[l*K + s], final_trace[l*K + s] for the
  *     s-th output pose (s < n_poses[l]; later slots get -inf / -1 / 0);
  *   pose_xyz: ligand l's pose s starts at float index 3*(atom_off[l]*K + s*n_l)
@@ -215,7 +217,7 @@ typedef struct {
     int32_t *status;          /* [L] dock_ligand_status */
     float *pose_score;        /* [L*K] */
     int32_t *pose_restart;    /* [L*K] */
-    float *pose_xyz;          /* [n_atoms_total*K*3] */
+    float *pose_xyz;          /* [n_atoms_total*K*3] or NULL */
     float *restart_score;     /* [L*R] or NULL */
     uint16_t *trace;          /* [R*(L + P*n_rot_total)] or NULL */
     uint16_t *final_trace;    /* [L*K] or NULL */

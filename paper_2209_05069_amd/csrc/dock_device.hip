@@ -2128,7 +2128,7 @@ __global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArg
         }
         __syncthreads();
         const float *acc = ws.acc_pose + (size_t)a0 * K * 3;
-        for (int s = wave; s < ns; s += W) {
+        for (int s = wave; s < ns && out.pxyz; s += W) {
             Pose<NS> Y;
 #pragma unroll
             for (int q = 0; q < NS; ++q) {
@@ -2151,7 +2151,7 @@ __global__ __launch_bounds__(256) void k_out(SearchArgs sa, LibArgs lib, WorkArg
             }
         }
         const int per = 3 * n;
-        for (int e = threadIdx.x; e < (K - ns) * per; e += blockDim.x)
+        for (int e = threadIdx.x; out.pxyz && e < (K - ns) * per; e += blockDim.x)
             out.pxyz[((size_t)a0 * K + (size_t)ns * n) * 3 + e] = 0.f;
         for (int s = ns + (int)threadIdx.x; s < K; s += blockDim.x) {
             out.pscore[(size_t)l * K + s] = -INFINITY;

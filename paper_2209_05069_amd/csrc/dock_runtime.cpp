@@ -134,6 +134,7 @@ struct Ticket {
     int L = 0, K = 0, R = 0;
     long long A = 0, trace_len = 0;
     void *pinned = nullptr;          // pinned inputs followed by the results
+    size_t pinned_cap = 0;           // its capacity (it returns to the pinned pool)
     void *host_stage = nullptr;      // results part of `pinned`
     size_t dev_bytes = 0;            // device memory held until the ticket retires
     hipStream_t stream = nullptr;    // submit stream the request runs on
@@ -164,6 +165,9 @@ struct dock_ctx {
     std::vector<hipStream_t> submit_streams;  // dock_submit: requests round-robin over these
     size_t next_submit = 0;
     std::map<uint64_t, Ticket> tickets;
+    // pinned staging buffers of retired tickets, kept for reuse: capacity -> buffer
+    std::multimap<size_t, void *> pinned_pool;
+    size_t pinned_pool_bytes = 0;
     uint64_t next_ticket = 1;
     size_t reserve_bytes = (size_t)1 << 30;
     size_t budget = 0;         // dock_submit admission budget (0: free memory less the reserve)
@@ -237,8 +241,10 @@ int check_library_shape(const dock_library *lib) {
 int check_results(const dock_results *o, int n_ligands) {
     if (!o) return fail(DOCK_EINVAL, "results is NULL");
     if (n_ligands > 0 && (!o->best_score || !o->n_poses || !o->status || !o->pose_score ||
-                          !o->pose_restart || !o->pose_xyz))
+                          !o->pose_restart))
         return fail(DOCK_EINVAL, "a required result array is NULL");
+    if (o->pose_contacts && !o->pose_xyz)
+        return fail(DOCK_EINVAL, "pose_contacts needs pose_xyz (the contacts are of the output poses)");
     return DOCK_OK;
 }
 
@@ -419,7 +425,7 @@ SubmitLayout submit_layout(const dock_library *lib, const dock_params *p, const 
     t->o_st = stake((size_t)L * 4);
     t->o_ps = stake((size_t)L * K * 4);
     t->o_pr = stake((size_t)L * K * 4);
-    t->o_xyz = stake((size_t)A * K * 12);
+    t->o_xyz = stake(o->pose_xyz ? (size_t)A * K * 12 : 0);
     t->o_rs = stake(o->restart_score ? (size_t)L * R * 4 : 0);
     t->o_tr = stake((size_t)trace_len * 2);
     t->o_ft = stake(o->final_trace ? (size_t)L * K * 2 : 0);
@@ -437,6 +443,41 @@ int occupancy(dock_ctx *c, const std::string &key, int v) {
 }
 
 constexpr int kOutBlocksPerCu = 4;
+constexpr size_t kPinnedPoolMax = (size_t)1 << 30;  // pinned bytes kept for reuse at most
+
+// Pinned staging memory for a dock_submit request: a retired ticket's buffer of
+// at least `bytes` (and not far larger) when the pool has one, else a new one
+// with a quarter more room.  Pinning fresh pages costs milliseconds per request.
+int pinned_get(dock_ctx *c, size_t bytes, void **out, size_t *cap) {
+    auto it = c->pinned_pool.lower_bound(bytes);
+    if (it != c->pinned_pool.end() && it->first <= 4 * bytes + ((size_t)1 << 20)) {
+        *out = it->second;
+        *cap = it->first;
+        c->pinned_pool_bytes -= it->first;
+        c->pinned_pool.erase(it);
+        return DOCK_OK;
+    }
+    const size_t capb = bytes + bytes / 4;
+    if (hipHostMalloc(out, capb, hipHostMallocDefault) != hipSuccess) {
+        (void)hipGetLastError();
+        *out = nullptr;
+        return fail(DOCK_ENOMEM, "pinned staging allocation failed");
+    }
+    *cap = capb;
+    return DOCK_OK;
+}
+
+// Return a staging buffer whose copies have completed to the pool (or free it
+// when the pool is full).
+void pinned_put(dock_ctx *c, void *p, size_t cap) {
+    if (!p) return;
+    if (c->pinned_pool_bytes + cap > kPinnedPoolMax) {
+        (void)hipHostFree(p);
+        return;
+    }
+    c->pinned_pool.emplace(cap, p);
+    c->pinned_pool_bytes += cap;
+}
 
 constexpr int kPlainWaves = 4;
 constexpr int kPlainSelectWaves = 16;  // plain form: a ligand's candidates over 16 waves
@@ -868,6 +909,7 @@ int dock_destroy(dock_ctx *c) {
         if (kv.second.done) hipEventDestroy(kv.second.done);
         if (kv.second.pinned) hipHostFree(kv.second.pinned);
     }
+    for (auto &kv : c->pinned_pool) hipHostFree(kv.second);
     for (auto &kv : c->pockets) kv.second.release();
     if (c->d_scored) hipFree(c->d_scored);
     for (auto &kv : c->ws) hipFree(kv.second.base);
@@ -1377,12 +1419,14 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     // one pinned buffer per ticket: the inputs (same layout as on the device, so
     // one copy moves them all) followed by the results
     void *pinned = nullptr;
-    if (hipHostMalloc(&pinned, off + (so > 0 ? so : 256), hipHostMallocDefault) != hipSuccess) {
+    size_t pcap = 0;
+    if (pinned_get(c, off + (so > 0 ? so : 256), &pinned, &pcap) != DOCK_OK) {
         hipFreeAsync(d, s);
-        return fail(DOCK_ENOMEM, "pinned staging allocation failed");
+        return DOCK_ENOMEM;
     }
     t.host_stage = (char *)pinned + off;
     t.pinned = pinned;
+    t.pinned_cap = pcap;
     // inputs are copied into pinned memory before return: the caller may free its own
     char *h = (char *)pinned;
     auto put = [&](size_t at, const void *src, size_t b) {
@@ -1402,7 +1446,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (e) {
         hipStreamSynchronize(s);
         hipFreeAsync(d, s);
-        hipHostFree(pinned);
+        pinned_put(c, pinned, pcap);
         return fail(DOCK_EDEVICE, std::string("input copy failed: ") + hipGetErrorString(e));
     }
     dock_library dl = *lib;
@@ -1421,7 +1465,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     dres.status = (int32_t *)(dr + t.o_st);
     dres.pose_score = (float *)(dr + t.o_ps);
     dres.pose_restart = (int32_t *)(dr + t.o_pr);
-    dres.pose_xyz = (float *)(dr + t.o_xyz);
+    dres.pose_xyz = o->pose_xyz ? (float *)(dr + t.o_xyz) : nullptr;
     dres.restart_score = o->restart_score ? (float *)(dr + t.o_rs) : nullptr;
     dres.trace = o->trace ? (uint16_t *)(dr + t.o_tr) : nullptr;
     dres.final_trace = o->final_trace ? (uint16_t *)(dr + t.o_ft) : nullptr;
@@ -1430,7 +1474,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (rc2) {
         hipStreamSynchronize(s);
         hipFreeAsync(d, s);
-        hipHostFree(pinned);
+        pinned_put(c, pinned, pcap);
         return rc2;
     }
     e = hipMemcpyAsync(t.host_stage, dr, so, hipMemcpyDeviceToHost, s);
@@ -1439,7 +1483,7 @@ int dock_submit(dock_ctx *c, int32_t pocket, const dock_library *lib, const dock
     if (!e) e = hipEventRecord(t.done, s);
     if (e) {
         hipStreamSynchronize(s);
-        hipHostFree(pinned);
+        pinned_put(c, pinned, pcap);
         return fail(DOCK_EDEVICE, std::string("enqueue failed: ") + hipGetErrorString(e));
     }
     t.pocket = pocket;
@@ -1481,14 +1525,14 @@ static int finish_ticket(dock_ctx *c, std::map<uint64_t, Ticket>::iterator it) {
         std::memcpy(u.status, h + t.o_st, L * 4);
         std::memcpy(u.pose_score, h + t.o_ps, L * K * 4);
         std::memcpy(u.pose_restart, h + t.o_pr, L * K * 4);
-        std::memcpy(u.pose_xyz, h + t.o_xyz, (size_t)t.A * K * 12);
+        if (u.pose_xyz) std::memcpy(u.pose_xyz, h + t.o_xyz, (size_t)t.A * K * 12);
         if (u.restart_score) std::memcpy(u.restart_score, h + t.o_rs, L * R * 4);
         if (u.trace) std::memcpy(u.trace, h + t.o_tr, (size_t)t.trace_len * 2);
         if (u.final_trace) std::memcpy(u.final_trace, h + t.o_ft, L * K * 2);
         if (u.pose_contacts) std::memcpy(u.pose_contacts, h + t.o_pc, L * K * 4);
     }
     hipEventDestroy(t.done);
-    hipHostFree(t.pinned);
+    pinned_put(c, t.pinned, t.pinned_cap);
     c->inflight -= t.dev_bytes < c->inflight ? t.dev_bytes : c->inflight;
     c->stream_tickets[t.stream] -= 1;
     auto pk = c->pockets.find(t.pocket);

@@ -260,7 +260,7 @@ class DeviceResults:
 
     def __init__(self, n_ligands, n_atoms_total, n_rot_total, params: SearchParams,
                  device="cuda:0", restart_scores=False, trace=False, final_trace=False,
-                 contacts=False):
+                 contacts=False, poses=True):
         import torch
         L, K, R, Pp = n_ligands, params.top_k, params.restarts, params.sweep_passes
         self.L, self.K, self.R = L, K, R
@@ -270,7 +270,8 @@ class DeviceResults:
         self.status = torch.empty(L, dtype=i32, device=device)
         self.pose_score = torch.empty(L * K, dtype=f32, device=device)
         self.pose_restart = torch.empty(L * K, dtype=i32, device=device)
-        self.pose_xyz = torch.empty(n_atoms_total * K * 3, dtype=f32, device=device)
+        self.pose_xyz = (torch.empty(n_atoms_total * K * 3, dtype=f32, device=device)
+                         if poses else None)
         self.restart_score = torch.empty(L * R, dtype=f32, device=device) if restart_scores else None
         self.trace = (torch.empty(R * (L + Pp * n_rot_total), dtype=i16, device=device)
                       if trace else None)
@@ -301,14 +302,15 @@ class HostResults:
     """Host (numpy) result buffers for dock_submit."""
 
     def __init__(self, n_ligands, n_atoms_total, n_rot_total, params: SearchParams,
-                 restart_scores=False, trace=False, final_trace=False, contacts=False):
+                 restart_scores=False, trace=False, final_trace=False, contacts=False,
+                 poses=True):
         L, K, R, Pp = n_ligands, params.top_k, params.restarts, params.sweep_passes
         self.best_score = np.zeros(L, np.float32)
         self.n_poses = np.zeros(L, np.int32)
         self.status = np.zeros(L, np.int32)
         self.pose_score = np.zeros(L * K, np.float32)
         self.pose_restart = np.zeros(L * K, np.int32)
-        self.pose_xyz = np.zeros(n_atoms_total * K * 3, np.float32)
+        self.pose_xyz = np.zeros(n_atoms_total * K * 3, np.float32) if poses else None
         self.restart_score = np.zeros(L * R, np.float32) if restart_scores else None
         self.trace = np.zeros(R * (L + Pp * n_rot_total), np.uint16) if trace else None
         self.final_trace = np.zeros(L * K, np.uint16) if final_trace else None
@@ -441,8 +443,9 @@ def ligand_outputs(h, l, atom_off, rot_off, params: SearchParams):
     npose = int(h["n_poses"][l])
     out = dict(status=int(h["status"][l]), best_score=float(h["best_score"][l]), n_poses=npose,
                pose_score=h["pose_score"][l * K:l * K + npose].copy(),
-               pose_restart=h["pose_restart"][l * K:l * K + npose].copy(),
-               pose_xyz=h["pose_xyz"][3 * a0 * K:3 * (a0 * K + npose * n)].reshape(npose, n, 3).copy())
+               pose_restart=h["pose_restart"][l * K:l * K + npose].copy())
+    if h.get("pose_xyz") is not None:
+        out["pose_xyz"] = h["pose_xyz"][3 * a0 * K:3 * (a0 * K + npose * n)].reshape(npose, n, 3).copy()
     if h.get("restart_score") is not None:
         out["restart_score"] = h["restart_score"][l * R:(l + 1) * R].copy()
     if h.get("trace") is not None:

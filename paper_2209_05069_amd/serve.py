@@ -1,10 +1,16 @@
 """Screening service loop over the asynchronous C ABI (dock_submit / dock_poll).
 
 Requests (one ligand each, naming a device-resident pocket) arrive over time.
-Per pocket they collect in a bucket; a bucket is submitted when it holds
-`max_batch` ligands or its oldest request has waited `flush_ms` (so an
-underfilled bucket does not wait for ever), the way the paper's batched host
-fills buckets and launches them when full (Batched Implementation subsection).
+Per pocket they collect in a bucket.  Two submission policies:
+- size/age (max_inflight = 0): a bucket is submitted when it holds `max_batch`
+  ligands or its oldest request has waited `flush_ms` (so an underfilled bucket
+  does not wait for ever), the way the paper's batched host fills buckets and
+  launches them when full (Batched Implementation subsection);
+- work-conserving (max_inflight > 0): at most `max_inflight` batches are in
+  flight; whenever one finishes (or at once, when the device is idle) the
+  bucket whose oldest request has waited longest is submitted, up to
+  `max_batch` ligands.  Requests gather while the device is busy, so batches
+  grow with the load and stay small (low latency) when it is light.
 Admission is by free device memory: when dock_submit answers DOCK_EAGAIN the
 bucket stays queued and is retried after completions.  Every request's latency
 runs from its arrival to the moment its result is visible on the host.
@@ -48,8 +54,10 @@ class ServeStats:
 
 class Server:
     def __init__(self, ctx, pockets: dict, library, params: D.SearchParams, max_batch=1024,
-                 flush_ms=20.0):
+                 flush_ms=20.0, max_inflight=0, return_poses=False):
         self.ctx = ctx
+        self.return_poses = return_poses  # False: scores only (no pose coordinates moved)
+        self.max_inflight = max_inflight
         self.pockets = pockets            # key -> pocket id from dock_pocket_load
         self.lib = library                # host CSR library the requests index into
         self.params = params
@@ -68,7 +76,7 @@ class Server:
     def _submit(self, key, reqs, now):
         sub = self.lib.subset([r.ligand for r in reqs])
         res = D.HostResults(sub.n_ligands, int(sub.atom_off[-1]), int(sub.rot_off[-1]),
-                            self.params)
+                            self.params, poses=self.return_poses)
         try:
             t = D.dock_submit(self.ctx, self.pockets[key], sub, self.params, res)
         except D.DockError as e:
@@ -83,12 +91,24 @@ class Server:
     def pump(self, now=None):
         """Submit due buckets, collect finished batches.  Returns requests done now."""
         now = time.perf_counter() if now is None else now
-        for key, q in self.queues.items():
-            while q and (len(q) >= self.max_batch or now - q[0].t_arrival >= self.flush_s):
+        if self.max_inflight > 0:
+            while len(self.inflight) < self.max_inflight:
+                live = [(q[0].t_arrival, k) for k, q in self.queues.items() if q]
+                if not live:
+                    break
+                key = min(live)[1]
+                q = self.queues[key]
                 take = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
                 if not self._submit(key, take, now):
                     q.extendleft(reversed(take))
                     break
+        else:
+            for key, q in self.queues.items():
+                while q and (len(q) >= self.max_batch or now - q[0].t_arrival >= self.flush_s):
+                    take = [q.popleft() for _ in range(min(self.max_batch, len(q)))]
+                    if not self._submit(key, take, now):
+                        q.extendleft(reversed(take))
+                        break
         finished = 0
         still = []
         for b in self.inflight:

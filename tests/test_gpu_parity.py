@@ -443,17 +443,25 @@ def test_serving_loop_maps_results_to_requests(D, ctx):
     rng = np.random.default_rng(370)
     reqs = [S.Request(i, int(rng.integers(0, 3)), int(rng.integers(0, lib.n_ligands)), 0.0)
             for i in range(120)]
-    print("[case] serving loop, 120 requests over 3 pockets", flush=True)
-    srv = S.Server(ctx, pids, lib, params, max_batch=16, flush_ms=2.0)
-    r = S.run(srv, reqs, S.poisson_arrivals(2000.0, len(reqs), 370), time_limit_s=60.0)
-    assert r["completed"] == len(reqs)
+    servers = []
+    for kw in (dict(max_batch=16, flush_ms=2.0),                       # size/age buckets
+               dict(max_batch=16, max_inflight=2),                     # work-conserving
+               dict(max_batch=16, max_inflight=3, return_poses=True)):
+        print(f"[case] serving loop, 120 requests over 3 pockets, {kw}", flush=True)
+        for rq in reqs:
+            rq.t_arrival = 0.0
+        srv = S.Server(ctx, pids, lib, params, **kw)
+        r = S.run(srv, reqs, S.poisson_arrivals(2000.0, len(reqs), 370), time_limit_s=60.0)
+        assert r["completed"] == len(reqs)
+        servers.append(srv)
     for p in range(3):
         D.dock_pocket_unload(ctx, pids[p])
     for p, pk in enumerate(pockets):
         h, _ = run_batch(D, ctx, pk, lib, q, **s)
         for req in reqs:
             if req.pocket == p:
-                assert srv.results[req.rid] == h["best_score"][req.ligand], req
+                for srv in servers:
+                    assert srv.results[req.rid] == h["best_score"][req.ligand], req
 
 
 def test_autotune_reports_every_bin_and_keeps_results(D, ctx):

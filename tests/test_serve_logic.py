@@ -68,3 +68,28 @@ def test_poisson_arrivals_rate():
     a = S.poisson_arrivals(1000.0, 20000, 3)
     assert np.all(np.diff(a) > 0)
     assert abs(20000 / a[-1] - 1000.0) < 30
+
+
+def test_work_conserving_policy_caps_inflight_and_takes_oldest_first(fake):
+    fake.refuse, fake.delay = 0, 3   # a batch finishes on its third poll
+    lib = synth.library_uniform(6, 60, (10, 20), (1, 3))
+    q = synth.start_quats(6, 4)
+    params = D.SearchParams(q, torsion_steps=8, top_k=2)
+    srv = S.Server(None, {0: 21, 1: 22, 2: 23}, lib, params, max_batch=16, max_inflight=2)
+    # an idle device takes a lone request at once, without waiting for a flush
+    srv.add(S.Request(0, 1, 0, 0.0))
+    srv.pump(now=0.0)
+    assert fake.sizes == [1] and fake.pockets == [22]
+    # while the device is busy, requests gather; oldest bucket first, then next
+    for i in range(1, 31):
+        srv.add(S.Request(i, [2, 0, 1][i % 3], i, 0.001 * i))
+    srv.pump(now=0.05)               # one slot free: the oldest head (request 1) is pocket 0's
+    assert len(srv.inflight) == 2
+    assert fake.pockets[-1] == 21 and fake.sizes[-1] == 10
+    for _ in range(3):
+        srv.pump(now=0.06)
+    assert len(fake.sizes) >= 4 and max(fake.sizes) <= 16
+    for _ in range(10):
+        srv.pump(now=0.1)
+    assert srv.idle() and srv.stats.done == 31
+    assert sorted(fake.sizes) == [1, 10, 10, 10]
