@@ -1016,7 +1016,8 @@ __device__ __forceinline__ BandGeom band_geom(int b, float ecy, float ecz) {
 }
 
 // Atlas pass 1 (one workgroup of 1024 per band): band geometry and column count.
-// info[2b] = (y0, z0, thy, thz), info[2b+1] = (rows, ncols or -1, table bytes, 0).
+// info[2b] = (y0, z0, thy, thz), info[2b+1] = (rows, ncols or -1, table bytes, 0);
+// pass 2 sets info[2b+1].w to the band's row split (see k_atlas_fill).
 __global__ __launch_bounds__(1024) void k_atlas_count(GridArgs g, int4 *info) {
     __shared__ int wsum[16];
     const int b = blockIdx.x, tid = threadIdx.x, lane = lane_id(), wave = tid >> 6;
@@ -1041,7 +1042,8 @@ __global__ __launch_bounds__(1024) void k_atlas_count(GridArgs g, int4 *info) {
     if (tid == 0) {
         int total = 0;
         for (int w = 0; w < (int)(blockDim.x >> 6); ++w) total += wsum[w];
-        const bool ok = per <= kShellRowsPerThread && total < (1 << 14);
+        // entries hold (first column - first cell + kEntryBias) in 16 bits
+        const bool ok = per <= kShellRowsPerThread && total < (1 << 15);
         info[2 * b] = make_int4(q.y0, q.z0, q.thy, q.thz);
         info[2 * b + 1] = make_int4(rows, ok ? total : -1, (rows * 8 + 15) & ~15, 0);
     }
@@ -1049,8 +1051,13 @@ __global__ __launch_bounds__(1024) void k_atlas_count(GridArgs g, int4 *info) {
 
 // Atlas pass 2 (one workgroup of 1024 per (type, band)): the row table and the
 // face columns of the band, from the cell cubes.  blob16[t*nb + b] is the
-// band's offset in float4 units.
-__global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *info,
+// band's offset in float4 units.  The columns are stored row by row, so the
+// column index C1 at which the first row starts whose columns begin at or past
+// half the band splits it into two chunks, each a run of whole rows (both
+// columns of every cell in one chunk); the type-0 workgroup writes C1 into
+// info[2b+1].w (k_align streams a band larger than its LDS region in two
+// chunks of the same table).
+__global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, int4 *info,
                                                      const int *blob16, float4 *atlas, int nb) {
     __shared__ int pre[kShellRowsPerThread * 1024 + 1];
     __shared__ int wsum[16];
@@ -1101,6 +1108,13 @@ __global__ __launch_bounds__(1024) void k_atlas_fill(GridArgs g, const int4 *inf
         }
     }
     __syncthreads();
+    if (t == 0) {
+        // C1 = pre[r] for the first row r with pre[r] >= ncols / 2 (a row boundary)
+        for (int r = tid; r < rows; r += BD) {
+            const bool first = pre[r] >= i1.y / 2 && (r == 0 || pre[r - 1] < i1.y / 2);
+            if (first) info[2 * b + 1].w = pre[r];
+        }
+    }
     for (int v = tid; v < i1.y; v += BD) {
         int lo = 0, hi = rows - 1;  // last row whose first column is <= v
         while (lo < hi) {
@@ -1316,6 +1330,73 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
     }
 }
 
+// shell_batch_in for a band of which only columns [lo, hi) are resident (a band
+// streamed in two chunks of whole rows): a sample whose column lies in the
+// resident chunk reads it, the others read the zero pair and add +0.  Each
+// sample's column lies in exactly one chunk and the two passes of an atom run
+// before the next atom, so every accumulator gets each sample once, in atom
+// order, and +0 never changes a sum (sums start at +0 and never become -0).
+template <int JM>
+__device__ __forceinline__ void shell_batch_part(float (&v)[kShellBatch], const Shell &s,
+                                                 const float (&gx)[kShellBatch], float gy,
+                                                 const float (&gz)[kShellBatch], int lo, int hi) {
+    static_assert(align_global_count(JM) == 0, "no global slots in a chunked band");
+    const float fy = __builtin_amdgcn_fractf(gy);
+    float fx[kShellBatch], fz[kShellBatch];
+    int2 e2[kShellBatch];
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) {
+        fx[k] = __builtin_amdgcn_fractf(gx[k]);
+        fz[k] = __builtin_amdgcn_fractf(gz[k]);
+        const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz[k];
+        e2[k] = s.table0[min(max(ra, s.koff), s.klast)];
+    }
+    float4 q0[kShellBatch], q1[kShellBatch];
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) {
+        const int e = gx[k] < s.cx ? e2[k].x : e2[k].y;
+        const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx[k], s.maxcol);
+        const float4 *q = (unsigned)(c - lo) < (unsigned)(hi - lo) ? s.col + c : s.zero;
+        q0[k] = q[0];
+        q1[k] = q[1];
+    }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int k = 0; k < kShellBatch; ++k) v[k] = tri_blend(q0[k], q1[k], fx[k], fy, fz[k]);
+}
+
+// shell_atom<JM, true> over the resident chunk [lo, hi) of the atom's band.
+template <int JM>
+__device__ __forceinline__ void shell_atom_part(float (&acc)[JM], const Shell &sh,
+                                                const XStage &xs, cfloat2_p cj, int jw, float ex,
+                                                float ez, int lo, int hi) {
+#pragma unroll
+    for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
+        if (j0 < jw) {
+            float gx[kShellBatch], gz[kShellBatch], v[kShellBatch];
+#pragma unroll
+            for (int k = 0; k < kShellBatch; ++k) {
+                const float2 c = ld_cs(cj, j0 + k);
+                gx[k] = align_gx(xs, c, ex);
+                gz[k] = align_gz(xs, c, ez);
+            }
+            shell_batch_part<JM>(v, sh, gx, xs.gy, gz, lo, hi);
+#pragma unroll
+            for (int k = 0; k < kShellBatch; ++k) acc[j0 + k] += v[k];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+    }
+#pragma unroll
+    for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
+}
+
+// Float4 count of the first copy of an atom's band (c0, c1 from k_align's ainf):
+// the whole band, or for a band in two chunks its table and first chunk.
+__device__ __forceinline__ int band_copy16(const int4 &c0, const int4 &c1) {
+    const int C1 = c1.w >> 1;
+    return C1 > 0 ? band_padded(c1.z + C1) : band_padded(c0.y);
+}
+
 // Persistent workgroups pop (ligand, group of GR restarts) items of one size bin
 // and write each restart's best orientation as the first entry of its decision
 // trace; k_dock then starts from it.  A lane holds a strip: one restart, one x
@@ -1418,6 +1499,14 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     if (gj.y >= 0 && band_padded(size16) <= region16) {
                         c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
                         c1 = make_int4(gi.z, gi.w, gj.z / 16, inside ? 1 : 0);
+                    } else if (gj.y >= 0 && inside && gj.w > 0 &&
+                               band_padded(gj.z / 16 + gj.w) <= region16 &&
+                               gj.z / 16 + band_padded(gj.y - gj.w) <= region16) {
+                        // too large for the region: two chunks of whole rows, columns
+                        // [0, C1) and [C1, ncols), each resident with the table
+                        // (c1.w: bit 0 inside, bits 1.. C1)
+                        c0 = make_int4(g.blob16[t * g.nbands + b], size16, gi.x, gi.y);
+                        c1 = make_int4(gi.z, gi.w, gj.z / 16, 1 | (gj.w << 1));
                     }
                 }
                 ainf[2 * a] = c0;
@@ -1446,20 +1535,27 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             {
                 const int4 c0 = ainf[0];
                 if (c0.x >= 0) {
-                    const int sz = band_padded(c0.y);
+                    const int sz = band_copy16(c0, ainf[1]);
                     for (int k = tid; k < sz; k += BD) region[k] = g.atlas[c0.x + k];
                 }
             }
             __syncthreads();
             for (int a = 0; a < n; ++a) {
                 const int4 cn = a + 1 < n ? ainf[2 * (a + 1)] : make_int4(-1, 0, 0, 0);
+                const int4 cn1 = a + 1 < n ? ainf[2 * (a + 1) + 1] : make_int4(0, 0, 0, 0);
                 const int4 c0 = ainf[2 * a], c1 = ainf[2 * a + 1];
-                // Where the next band goes: when both fit, at the other end of the
-                // region, streamed by the copier wave while this atom is sampled;
-                // else at the start, copied by everyone after the barrier.
+                // A band in two chunks fills the region (its first chunk and table at
+                // the start, the second chunk after the table) and is never double
+                // buffered.  Where the next band (or first chunk) goes: when both fit,
+                // at the other end of the region, streamed by the copier wave while
+                // this atom is sampled; else at the start, copied by everyone after the
+                // barrier.
+                const int C1 = c1.w >> 1;
+                const bool two = c0.x >= 0 && C1 > 0;
+                const bool next_two = cn.x >= 0 && (cn1.w >> 1) > 0;
                 const int sa_ = c0.x >= 0 ? band_padded(c0.y) : 0;
-                const int sn = cn.x >= 0 ? band_padded(cn.y) : 0;
-                const bool dbl = cn.x >= 0 && sa_ + sn <= region16;
+                const int sn = cn.x >= 0 ? band_copy16(cn, cn1) : 0;
+                const bool dbl = cn.x >= 0 && !two && !next_two && sa_ + sn <= region16;
                 const int offN = dbl ? (offA == 0 ? region16 - sn : 0) : 0;
                 if (won) {
                     const float4 d = dxyz[a];
@@ -1485,7 +1581,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.table0 = sh.table - sh.koff;
                         sh.col = region + offA + c1.z;
                         sh.zero = zero2;
-                        if (c1.w) shell_atom<JM, true>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
+                        if (two) shell_atom_part<JM>(acc, sh, xs, cj, jw, ce.x, ce.z, 0, C1);
+                        else if (c1.w) shell_atom<JM, true>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
                         else shell_atom<JM, false>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
                     } else if (c1.w) {
 #pragma unroll
@@ -1516,6 +1613,37 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     __builtin_amdgcn_s_waitcnt(0);
                 }
                 __syncthreads();  // every sample of atom a has read the region
+                if (two) {
+                    // second chunk: columns [C1, ncols) after the table, then the
+                    // samples whose columns lie there
+                    const int nB = band_padded(c0.y - c1.z - C1);
+                    for (int k = tid; k < nB; k += BD) region[c1.z + k] = g.atlas[c0.x + c1.z + C1 + k];
+                    __syncthreads();
+                    if (won) {
+                        const float4 d = dxyz[a];
+                        const float yx = fmaf(m0.x, d.x, fmaf(m0.y, d.y, fmaf(m0.z, d.z, g.cx)));
+                        const float yy = fmaf(m1.x, d.x, fmaf(m1.y, d.y, fmaf(m1.z, d.z, g.cy)));
+                        const float yz = fmaf(m2.x, d.x, fmaf(m2.y, d.y, fmaf(m2.z, d.z, g.cz)));
+                        const XStage xs = align_x((yx - cw.x) * g.inv_h, (yy - cw.y) * g.inv_h,
+                                                  (yz - cw.z) * g.inv_h, ci, ce.y);
+                        Shell sh;
+                        sh.y0 = c0.z;
+                        sh.z0 = c0.w;
+                        sh.thy = c1.x;
+                        sh.thz = c1.y;
+                        sh.rows = c1.x * c1.y;
+                        sh.maxcol = c0.y - c1.z - 2;
+                        sh.cx = g.acx;
+                        sh.koff = (unsigned)(c0.z * c1.y + c0.w);
+                        sh.klast = sh.koff + (unsigned)(sh.rows - 1);
+                        sh.table = (const int2 *)region;
+                        sh.table0 = sh.table - sh.koff;
+                        sh.col = region + c1.z - C1;  // column c >= C1 at region + c1.z + (c - C1)
+                        sh.zero = zero2;
+                        shell_atom_part<JM>(acc, sh, xs, cj, jw, ce.x, ce.z, C1, c0.y - c1.z);
+                    }
+                    __syncthreads();
+                }
                 if (cn.x >= 0 && !dbl) {  // the next atom's band, at the start
                     for (int k = tid; k < sn; k += BD) region[k] = g.atlas[cn.x + k];
                     __syncthreads();
@@ -2437,7 +2565,7 @@ hipError_t launch_atlas_count(const GridArgs &g, int4 *info, hipStream_t s) {
     return hipGetLastError();
 }
 
-hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blob16, float4 *atlas,
+hipError_t launch_atlas_fill(const GridArgs &g, int4 *info, const int *blob16, float4 *atlas,
                              int nb, hipStream_t s) {
     if (nb <= 0) return hipSuccess;
     hipLaunchKernelGGL(k_atlas_fill, dim3(nb * g.ntypes), dim3(1024), 0, s, g, info, blob16, atlas,

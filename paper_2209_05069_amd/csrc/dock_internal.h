@@ -38,7 +38,8 @@ struct GridArgs {
     float m2x, m2y, m2z;   // n-2 per axis
     float fnx, fslab;      // nx and nx*ny as floats
     // Shell atlas (see k_align): per radius band b < nbands, bands[2b] = (y0, z0,
-    // rows in y, rows in z), bands[2b+1] = (rows, columns or -1, table bytes, 0);
+    // rows in y, rows in z), bands[2b+1] = (rows, columns or -1, table bytes,
+    // C1: the column at which the band's second chunk starts);
     // blob16[t*nbands + b] = float4 offset of type t's band in `atlas`.
     const float4 *atlas;
     const int4 *bands;
@@ -140,7 +141,7 @@ constexpr int kMaxBands = 240;
 // with one 16-byte load per lane).
 __host__ __device__ inline int band_padded(int size16) { return (size16 + 63) & ~63; }
 hipError_t launch_atlas_count(const GridArgs &g, int4 *info, hipStream_t s);
-hipError_t launch_atlas_fill(const GridArgs &g, const int4 *info, const int *blob16, float4 *atlas,
+hipError_t launch_atlas_fill(const GridArgs &g, int4 *info, const int *blob16, float4 *atlas,
                              int nb, hipStream_t s);
 // Batched alignment of a bin's ligands (k_align), `arena` bytes of LDS per
 // workgroup.

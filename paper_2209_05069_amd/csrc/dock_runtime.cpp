@@ -830,18 +830,22 @@ int build_atlas(dock_ctx *c, Pocket &pk) {
     int nb = 0;
     long long off = 0;
     std::vector<int> blob((size_t)g.ntypes * kMaxBands);
+    // bands up to twice the LDS arena: the alignment kernel streams a band that
+    // does not fit its region in two chunks of whole rows
     for (; nb < kMaxBands; ++nb) {
         const int4 q = info[2 * nb + 1];
         const long long size16 = band_padded(q.z / 16 + q.y);
-        if (q.y < 0 || size16 * 16 > (long long)c->lds_arena) break;
+        if (q.y < 0 || size16 * 16 > 2LL * c->lds_arena) break;
     }
     for (int t = 0; t < g.ntypes; ++t)
         for (int b = 0; b < nb; ++b) {
             blob[(size_t)t * nb + b] = (int)off;
             off += band_padded(info[2 * b + 1].z / 16 + info[2 * b + 1].y);
         }
-    if (nb == 0 || off >= (1LL << 31)) return DOCK_OK;
-    if (hipMalloc(&pk.d_atlas, (size_t)off * 16) != hipSuccess ||
+    if (nb == 0 || off >= (1LL << 31) - 64) return DOCK_OK;
+    // 64 float4 of padding after the last band: a chunk copy reads whole 64-float4
+    // instructions from its start, which for a second chunk may pass its band's end
+    if (hipMalloc(&pk.d_atlas, (size_t)(off + 64) * 16) != hipSuccess ||
         hipMalloc(&pk.d_blob16, (size_t)g.ntypes * nb * sizeof(int)) != hipSuccess) {
         (void)hipGetLastError();
         return fail(DOCK_ENOMEM, "atlas allocation failed");
