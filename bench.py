@@ -78,6 +78,9 @@ def parse():
                          "device and search settings) instead of autotuning")
     ap.add_argument("--tune-ligands", type=int, default=4096,
                     help="ligands of the size-stratified sample the per-bin autotuner times on")
+    ap.add_argument("--graph-steps", type=int, default=2,
+                    help="steps replayed from the captured hipGraph after the timed region "
+                         "(phase timing off, on a stream of its own), reported as graph_replay (0: skip)")
     ap.add_argument("--bin-mode", type=int, default=0, choices=(0, 1),
                     help="work lists of the batched form: 0 = size bins of 32 heavy atoms, "
                          "1 = the paper's buckets (size bin x group of 4 rotatable bonds)")
@@ -520,6 +523,24 @@ def main():
     D.dock_set_timing(ctx, False)
     print(f"[bench] timed {a.steps} steps: {total_ms:.1f} ms; phases {tm}", file=sys.stderr,
           flush=True)
+    graph_ms = None
+    if a.graph_steps > 0:
+        # without phase timing, a call repeated with the same arguments on the same
+        # (non-null) stream is captured once as a hipGraph and replayed: the first of
+        # these two calls runs eagerly, the second captures and launches the graph
+        gs = torch.cuda.Stream()
+        gs.wait_stream(stream)
+        for _ in range(2):
+            D.dock_ligands_batch(ctx, pid, dl, params, res, gs)
+        torch.cuda.synchronize()
+        g0 = _events(torch, gs)
+        for _ in range(a.graph_steps):
+            D.dock_ligands_batch(ctx, pid, dl, params, res, gs)
+        g1 = _events(torch, gs)
+        torch.cuda.synchronize()
+        graph_ms = g0.elapsed_time(g1) / a.graph_steps
+        print(f"[bench] {a.graph_steps} graph-replayed steps: {graph_ms:.1f} ms per step",
+              file=sys.stderr, flush=True)
 
     L = lib.n_ligands
     ms = total_ms / a.steps
@@ -578,6 +599,11 @@ def main():
                        "note": "batched form: every ligand of a step is submitted at its start "
                                "and completes with it, so a ligand's latency is the step's"},
         "phases_ms": {k: tm[k] / calls for k in ("prep_ms", "align_ms", "dock_ms", "final_ms")},
+        "graph_replay": None if graph_ms is None else {
+            "ms_per_step": graph_ms, "ligands_per_s": L / (graph_ms * 1e-3),
+            "steps": a.graph_steps,
+            "note": "the same step replayed from its captured hipGraph (phase timing off); the "
+                    "timed steps above run eagerly because they record phase events"},
         "roofline": {
             "bound": "alu",
             "achieved": achieved,
