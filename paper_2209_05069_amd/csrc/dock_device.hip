@@ -1154,7 +1154,63 @@ struct Shell {
     const int2 *table;    // [thy*thz] (low-side entry, high-side entry)
     const float4 *col;    // face columns
     const float4 *zero;   // two zero columns: a miss blends to +0
+    // The same band as LDS byte addresses, for the in-grid sample paths (unsigned
+    // arithmetic, so an address below the region start wraps and wraps back):
+    uint32_t t0b;         // absolute row 0 (the table's first row less koff rows)
+    uint32_t tlob, thib;  // the table's first and last rows
+    uint32_t colb;        // column c at colb + 16 (c + kEntryBias)
+    uint32_t cmaxb;       // maxcol + kEntryBias
+    uint32_t zerob;       // the zero pair
 };
+
+// LDS byte address of a pointer into shared memory, and loads from one.
+typedef int lds_i32x2 __attribute__((ext_vector_type(2)));
+typedef float lds_f32x4 __attribute__((ext_vector_type(4)));
+__device__ __forceinline__ uint32_t lds_addr(const void *p) {
+    return (uint32_t)(uintptr_t)(const __attribute__((address_space(3))) void *)p;
+}
+__device__ __forceinline__ int2 lds_ld_int2(uint32_t a) {
+    const lds_i32x2 v = *(const __attribute__((address_space(3))) lds_i32x2 *)a;
+    return make_int2(v.x, v.y);
+}
+__device__ __forceinline__ float4 lds_ld_float4(uint32_t a) {
+    const lds_f32x4 v = *(const __attribute__((address_space(3))) lds_f32x4 *)a;
+    return make_float4(v.x, v.y, v.z, v.w);
+}
+
+// Byte-address fields of a shell whose table starts at LDS address table_b and
+// whose column c lies at col_b + 16 c (rows, koff, maxcol already set).
+__device__ __forceinline__ void shell_bytes(Shell &s, uint32_t table_b, uint32_t col_b) {
+    s.tlob = table_b;
+    s.thib = table_b + 8u * (uint32_t)(s.rows - 1);
+    s.t0b = table_b - 8u * s.koff;
+    // wave-uniform and opaque, so that a column address stays one shift-and-add
+    // of the index
+    s.colb = (uint32_t)uniform_int((int)(col_b - 16u * (uint32_t)kEntryBias));
+    asm volatile("" : "+s"(s.colb));
+    s.cmaxb = (uint32_t)(s.maxcol + kEntryBias);
+}
+
+// x clamped to [lo, hi] in one instruction (lo <= hi).
+__device__ __forceinline__ uint32_t med3_u32(uint32_t x, uint32_t lo, uint32_t hi) {
+    uint32_t r;
+    asm("v_med3_u32 %0, %1, %2, %3" : "=v"(r) : "v"(x), "v"(lo), "v"(hi));
+    return r;
+}
+
+// Low 16 bits of a row entry pair's entry on the sample's side of the centre
+// (e.x when gx < cx, else e.y; cx wave-uniform): the compare, then one
+// sub-dword select that takes the low halves of both operands.
+__device__ __forceinline__ uint32_t side_lo16(int2 e, float gx, float cx) {
+    uint32_t r;
+    asm("v_cmp_gt_f32 vcc, %3, %4\n\t"
+        "v_cndmask_b32_sdwa %0, %2, %1, vcc dst_sel:DWORD dst_unused:UNUSED_PAD "
+        "src0_sel:WORD_0 src1_sel:WORD_0"
+        : "=v"(r)
+        : "v"(e.x), "v"(e.y), "s"(cx), "v"(gx)
+        : "vcc");
+    return r;
+}
 
 __device__ __forceinline__ float lerp_cell(const float4 *p, float fx, float fy, float fz) {
     return tri_blend(p[0], p[1], fx, fy, fz);
@@ -1217,12 +1273,15 @@ __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, floa
 // in phases so that a wave keeps every sample's reads in flight together:
 // fractions and row entries, then the cell columns (LDS band, or the cube in
 // global memory for the slots is_global_slot picks), then the blends.  Each
-// value is the one shell_sample<true> or tri_in gives.
+// value is the one shell_sample<true> or tri_in gives: fy is the fraction of gy
+// and rowy the byte address of row (int) gy * thz of the table (both per atom);
+// the row and column indices are those of shell_sample<true>, clamped the same
+// way, computed as LDS byte addresses.
 template <int JM>
 __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, const Shell &s,
                                                const Tri &t, const float (&gx)[kShellBatch],
-                                               float gy, const float (&gz)[kShellBatch], int to) {
-    const float fy = __builtin_amdgcn_fractf(gy);
+                                               float gy, float fy, uint32_t rowy,
+                                               const float (&gz)[kShellBatch], int to) {
     float fx[kShellBatch], fz[kShellBatch];
     uint32_t off[kShellBatch];
     int2 e2[kShellBatch];
@@ -1234,8 +1293,7 @@ __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, 
             off[k] = in_cell(t, gx[k], gy, gz[k]);
         } else {
             // absolute row iy*thz + iz, clamped to the table's rows
-            const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz[k];
-            e2[k] = s.table0[min(max(ra, s.koff), s.klast)];
+            e2[k] = lds_ld_int2(med3_u32(rowy + ((uint32_t)(int)gz[k] << 3), s.tlob, s.thib));
         }
     }
     float4 q0[kShellBatch], q1[kShellBatch];
@@ -1245,16 +1303,22 @@ __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, 
             q0[k] = ldq(t.rs, off[k], to);
             q1[k] = ldq(t.rs, off[k], to + 16);
         } else {
-            const int e = gx[k] < s.cx ? e2[k].x : e2[k].y;
-            const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx[k], s.maxcol);
-            q0[k] = s.col[c];
-            q1[k] = s.col[c + 1];
+            const uint32_t c = min(side_lo16(e2[k], gx[k], s.cx) + (uint32_t)(int)gx[k], s.cmaxb);
+            const uint32_t a = s.colb + (c << 4);
+            q0[k] = lds_ld_float4(a);
+            q1[k] = lds_ld_float4(a + 16u);
         }
     }
     // every column read is issued before the first blend waits for one
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
     for (int k = 0; k < kShellBatch; ++k) v[k] = tri_blend(q0[k], q1[k], fx[k], fy, fz[k]);
+}
+
+// Per-atom inputs of shell_batch_in / shell_batch_part: the fraction of gy and
+// the byte address of table row (int) gy * thz.
+__device__ __forceinline__ uint32_t shell_rowy(const Shell &s, float gy) {
+    return s.t0b + (__umul24((uint32_t)(int)gy, (uint32_t)s.thz) << 3);
 }
 
 // The JM samples of one atom for one lane's strip (restart, x-rotation i, y
@@ -1269,6 +1333,8 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
                                            const XStage &xs, cfloat2_p cj, int jw, float ex,
                                            float ez, int to) {
     if (Inside) {
+        const float fy = __builtin_amdgcn_fractf(xs.gy);
+        const uint32_t rowy = shell_rowy(sh, xs.gy);
 #pragma unroll
         for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
             if (j0 < jw) {
@@ -1279,7 +1345,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
                     gx[k] = align_gx(xs, c, ex);
                     gz[k] = align_gz(xs, c, ez);
                 }
-                shell_batch_in<JM>(v, j0, sh, tr, gx, xs.gy, gz, to);
+                shell_batch_in<JM>(v, j0, sh, tr, gx, xs.gy, fy, rowy, gz, to);
 #pragma unroll
                 for (int k = 0; k < kShellBatch; ++k) acc[j0 + k] += v[k];
             }
@@ -1336,29 +1402,29 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
 // sample's column lies in exactly one chunk and the two passes of an atom run
 // before the next atom, so every accumulator gets each sample once, in atom
 // order, and +0 never changes a sum (sums start at +0 and never become -0).
+// plo = lo + kEntryBias and pn = hi - lo: the chunk in biased column indices;
+// the chunk test replaces the column clamp of shell_batch_in.
 template <int JM>
 __device__ __forceinline__ void shell_batch_part(float (&v)[kShellBatch], const Shell &s,
-                                                 const float (&gx)[kShellBatch], float gy,
-                                                 const float (&gz)[kShellBatch], int lo, int hi) {
+                                                 const float (&gx)[kShellBatch], float fy,
+                                                 uint32_t rowy, const float (&gz)[kShellBatch],
+                                                 uint32_t plo, uint32_t pn) {
     static_assert(align_global_count(JM) == 0, "no global slots in a chunked band");
-    const float fy = __builtin_amdgcn_fractf(gy);
     float fx[kShellBatch], fz[kShellBatch];
     int2 e2[kShellBatch];
 #pragma unroll
     for (int k = 0; k < kShellBatch; ++k) {
         fx[k] = __builtin_amdgcn_fractf(gx[k]);
         fz[k] = __builtin_amdgcn_fractf(gz[k]);
-        const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz[k];
-        e2[k] = s.table0[min(max(ra, s.koff), s.klast)];
+        e2[k] = lds_ld_int2(med3_u32(rowy + ((uint32_t)(int)gz[k] << 3), s.tlob, s.thib));
     }
     float4 q0[kShellBatch], q1[kShellBatch];
 #pragma unroll
     for (int k = 0; k < kShellBatch; ++k) {
-        const int e = gx[k] < s.cx ? e2[k].x : e2[k].y;
-        const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx[k], s.maxcol);
-        const float4 *q = (unsigned)(c - lo) < (unsigned)(hi - lo) ? s.col + c : s.zero;
-        q0[k] = q[0];
-        q1[k] = q[1];
+        const uint32_t c = side_lo16(e2[k], gx[k], s.cx) + (uint32_t)(int)gx[k];
+        const uint32_t a = c - plo < pn ? s.colb + (c << 4) : s.zerob;
+        q0[k] = lds_ld_float4(a);
+        q1[k] = lds_ld_float4(a + 16u);
     }
     __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
@@ -1370,6 +1436,9 @@ template <int JM>
 __device__ __forceinline__ void shell_atom_part(float (&acc)[JM], const Shell &sh,
                                                 const XStage &xs, cfloat2_p cj, int jw, float ex,
                                                 float ez, int lo, int hi) {
+    const float fy = __builtin_amdgcn_fractf(xs.gy);
+    const uint32_t rowy = shell_rowy(sh, xs.gy);
+    const uint32_t plo = (uint32_t)(lo + kEntryBias), pn = (uint32_t)(hi - lo);
 #pragma unroll
     for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
         if (j0 < jw) {
@@ -1380,7 +1449,7 @@ __device__ __forceinline__ void shell_atom_part(float (&acc)[JM], const Shell &s
                 gx[k] = align_gx(xs, c, ex);
                 gz[k] = align_gz(xs, c, ez);
             }
-            shell_batch_part<JM>(v, sh, gx, xs.gy, gz, lo, hi);
+            shell_batch_part<JM>(v, sh, gx, fy, rowy, gz, plo, pn);
 #pragma unroll
             for (int k = 0; k < kShellBatch; ++k) acc[j0 + k] += v[k];
         }
@@ -1388,6 +1457,19 @@ __device__ __forceinline__ void shell_atom_part(float (&acc)[JM], const Shell &s
     }
 #pragma unroll
     for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
+}
+
+// Copy by every wave of the workgroup (wave: its wave-uniform index of W): n16
+// float4 (a whole number of 64-float4 instructions) from src in global memory to
+// dst in LDS with direct global-to-LDS loads, all in flight before one wait; the
+// caller's barrier then publishes them.
+__device__ __forceinline__ void lds_fill(float4 *dst, const float4 *src, int n16, int wave, int W) {
+    const float4 *sl = src + lane_id();
+    for (int c = 64 * wave; c < n16; c += 64 * W)
+        __builtin_amdgcn_global_load_lds((const void *)(sl + c),
+                                         (__attribute__((address_space(3))) void *)(dst + c), 16, 0,
+                                         0);
+    __builtin_amdgcn_s_waitcnt(0);
 }
 
 // Float4 count of the first copy of an atom's band (c0, c1 from k_align's ainf):
@@ -1421,6 +1503,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     u64 *bestk = (u64 *)(smem + AlignLds::best(nmax, GR));
     float4 *region = (float4 *)(smem + AlignLds::region(nmax, GR));
     const int region16 = (arena - (int)AlignLds::region(nmax, GR)) / 16;
+    const uint32_t region_b = lds_addr(region), zero_b = lds_addr(zero2);
+    const int wave_u = uniform_int(wave);
     const Tri tr = make_tri(g);
     const int groups = (sa.R + GR - 1) / GR;
     const long long total = (long long)ws.counters[lst] * groups;
@@ -1536,7 +1620,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                 const int4 c0 = ainf[0];
                 if (c0.x >= 0) {
                     const int sz = band_copy16(c0, ainf[1]);
-                    for (int k = tid; k < sz; k += BD) region[k] = g.atlas[c0.x + k];
+                    lds_fill(region, g.atlas + c0.x, sz, wave_u, W);
                 }
             }
             __syncthreads();
@@ -1581,6 +1665,9 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.table0 = sh.table - sh.koff;
                         sh.col = region + offA + c1.z;
                         sh.zero = zero2;
+                        sh.zerob = zero_b;
+                        shell_bytes(sh, region_b + 16u * (uint32_t)offA,
+                                    region_b + 16u * (uint32_t)(offA + c1.z));
                         if (two) shell_atom_part<JM>(acc, sh, xs, cj, jw, ce.x, ce.z, 0, C1);
                         else if (c1.w) shell_atom<JM, true>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
                         else shell_atom<JM, false>(acc, sh, tr, xs, cj, jw, ce.x, ce.z, to);
@@ -1617,7 +1704,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     // second chunk: columns [C1, ncols) after the table, then the
                     // samples whose columns lie there
                     const int nB = band_padded(c0.y - c1.z - C1);
-                    for (int k = tid; k < nB; k += BD) region[c1.z + k] = g.atlas[c0.x + c1.z + C1 + k];
+                    lds_fill(region + c1.z, g.atlas + c0.x + c1.z + C1, nB, wave_u, W);
                     __syncthreads();
                     if (won) {
                         const float4 d = dxyz[a];
@@ -1640,12 +1727,14 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.table0 = sh.table - sh.koff;
                         sh.col = region + c1.z - C1;  // column c >= C1 at region + c1.z + (c - C1)
                         sh.zero = zero2;
+                        sh.zerob = zero_b;
+                        shell_bytes(sh, region_b, region_b + 16u * (uint32_t)(c1.z - C1));
                         shell_atom_part<JM>(acc, sh, xs, cj, jw, ce.x, ce.z, C1, c0.y - c1.z);
                     }
                     __syncthreads();
                 }
                 if (cn.x >= 0 && !dbl) {  // the next atom's band, at the start
-                    for (int k = tid; k < sn; k += BD) region[k] = g.atlas[cn.x + k];
+                    lds_fill(region, g.atlas + cn.x, sn, wave_u, W);
                     __syncthreads();
                 }
                 offA = offN;

@@ -17,7 +17,10 @@ constexpr int kMaxLists = kNumBins * kMaxGroups;  // work lists (atom bin x bond
 constexpr int kNumCounters = 4 * kMaxLists;  // per list: count, dock_next, select_next, align_next
 constexpr int kMaxTopK = 64;        // matches DOCK_MAX_TOP_K
 constexpr int kXcds = 8;            // gfx950: workgroups go round-robin to 8 XCDs of 32 CUs
-constexpr int kAlignJ = 32;         // k_align: y rotations per lane
+#ifndef DOCK_ALIGN_J
+#define DOCK_ALIGN_J 32
+#endif
+constexpr int kAlignJ = DOCK_ALIGN_J;  // k_align: y rotations per lane
 constexpr int kAlignMaxGroup = 64;  // k_align: restarts per item at most
 
 // The pocket is kept as cell cubes: cube (t,k,j,i) holds, for x = i and then
