@@ -928,7 +928,10 @@ __global__ __launch_bounds__(512) void k_dock(GridArgs g, SearchArgs sa, LibArgs
 // sample whose cell is not in the band reads its cube from global memory; both
 // give the same values, and the transform, blend and atom-order sum are those
 // of align_pose, so the scores are bit-identical.
-constexpr float kShellPad = 0.0625f;
+// The pad covers the rounding of a sample's distance from the grid centre (the
+// pose centroid lands there up to ~1e-5 cells, the turn keeps |r| up to a few
+// ulps): ~1e-4 cells at most, 200 times less than the pad.
+constexpr float kShellPad = 0.02f;
 constexpr float kBandWidth = 0.125f;
 constexpr int kShellRowsPerThread = 4;  // atlas kernels: rows per thread of 1024
 #ifndef DOCK_SHELL_BATCH
