@@ -250,7 +250,7 @@ int dock_ligands_batch(dock_ctx *ctx, int32_t pocket, const dock_library *lib,
  * of torsion (cos, sin), 8*(A rounded up to 32) B of alignment (cos, sin)) plus
  * the workspace (per atom 32 B of bump-pair rows and 12*top_k B of kept poses;
  * per ligand 4*R B of restart scores, 32 B of work lists (256 B with bin_mode 1)
- * and 12*top_k + 4 B of selection records; 1 KiB of counters;
+ * and 12*top_k + 4 B of selection records; 3 KiB of counters;
  * and, when out->trace is NULL, 2*R*(L + P*n_rot_total) B of decision trace),
  * each part rounded up to a multiple of 256 B.
  * Every call on a device shares that device's array and leaves its contents

@@ -1510,18 +1510,39 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
     const int wave_u = uniform_int(wave);
     const Tri tr = make_tri(g);
     const int groups = (sa.R + GR - 1) / GR;
-    const long long total = (long long)ws.counters[lst] * groups;
     const int Ws = W - 1;  // sampling waves; wave Ws copies bands
     const bool sampler = wave < Ws;
     // strips of one part padded to whole waves, so that j0 is wave-uniform
     const int spp = (GR * A + 63) & ~63, strips = parts * spp;
     if (tid < 2) zero2[tid] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // Items (ligand of the list, group of GR restarts), one queue per XCD: XCD x
+    // (workgroup b runs on XCD b % kXcds, the round-robin dispatch) takes the
+    // x-th contiguous share of the list's ligands with all their restart groups,
+    // so the groups of a ligand, which copy the same bands, read them through one
+    // L2.  A workgroup whose queue is empty takes items from the next queues.
+    const long long nl = ws.counters[lst];
+    int *qc = ws.counters + 4 * kMaxLists + lst * kXcds;
+    int qcur = (int)(blockIdx.x % kXcds), qleft = kXcds;  // thread 0's cursor
     for (;;) {
-        if (tid == 0) misc[0] = atomicAdd(&ws.counters[3 * kMaxLists + lst], 1);
+        if (tid == 0) {
+            int qli = -1, qgrp = 0;
+            while (qleft > 0) {
+                const long long l0 = nl * qcur / kXcds, l1 = nl * (qcur + 1) / kXcds;
+                const int got = atomicAdd(&qc[qcur], 1);
+                if ((long long)got < (l1 - l0) * groups) {
+                    qli = (int)(l0 + got / groups);
+                    qgrp = got % groups;
+                    break;
+                }
+                qcur = qcur + 1 == kXcds ? 0 : qcur + 1;
+                --qleft;
+            }
+            misc[0] = qli;
+            misc[1] = qgrp;
+        }
         __syncthreads();
-        const int item = misc[0];
-        if ((long long)item >= total) break;
-        const int li = item / groups, grp = item - li * groups;
+        const int li = misc[0], grp = misc[1];
+        if (li < 0) break;
         const int l = ws.bin_list[(size_t)lst * lib.L + li];
         const int a0 = lib.atom_off[l], n = lib.atom_off[l + 1] - a0;
         const int B = lib.rot_off[l + 1] - lib.rot_off[l];

@@ -14,9 +14,11 @@ constexpr int kFarWords = 4;        // far-pair rows: 4 x 64 bits per atom
 constexpr uint16_t kTraceNone = 0xFFFFu;
 constexpr int kMaxGroups = 8;       // paper buckets: rotatable bonds in groups of 4 (last: 28+)
 constexpr int kMaxLists = kNumBins * kMaxGroups;  // work lists (atom bin x bond group)
-constexpr int kNumCounters = 4 * kMaxLists;  // per list: count, dock_next, select_next, align_next
+
 constexpr int kMaxTopK = 64;        // matches DOCK_MAX_TOP_K
 constexpr int kXcds = 8;            // gfx950: workgroups go round-robin to 8 XCDs of 32 CUs
+// per list: count, dock_next, select_next, (unused), then one alignment queue per XCD
+constexpr int kNumCounters = (4 + kXcds) * kMaxLists;
 #ifndef DOCK_ALIGN_J
 #define DOCK_ALIGN_J 32
 #endif
@@ -79,7 +81,8 @@ struct LibArgs {
 struct WorkArgs {
     unsigned long long *far;  // [A_total][kFarWords]
     int *counters;            // [kNumCounters]: [4][kMaxLists] count, dock_next, select_next,
-                              // align_next of each work list
+                              // (unused) of each work list, then [kMaxLists][kXcds] the
+                              // alignment queues of each list
     int *bin_list;            // [lists][L] ligands of each work list
     float *rscore;            // [L][R]
     uint16_t *rtrace;         // [R*(L + P*Nr_total)]
