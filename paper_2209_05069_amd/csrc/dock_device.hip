@@ -1152,8 +1152,7 @@ struct AlignLds {
 struct Shell {
     int y0, z0, thy, thz, rows, maxcol;
     float cx;             // centre x (grid units): side of a sample
-    unsigned koff, klast; // absolute row index y0*thz + z0 of the first and last rows
-    const int2 *table0;   // table - koff: indexed by the absolute row index
+    unsigned koff;        // absolute row index y0*thz + z0 of the first row
     const int2 *table;    // [thy*thz] (low-side entry, high-side entry)
     const float4 *col;    // face columns
     const float4 *zero;   // two zero columns: a miss blends to +0
@@ -1229,34 +1228,12 @@ __device__ __forceinline__ const float4 *shell_cols(const Shell &s, int2 e2, flo
     return hit ? s.col + ((int)(e & 0xFFFFu) - kEntryBias + ix) : s.zero;
 }
 
-// Trilinear sample of grid coordinates (gx,gy,gz) from the shell; a cell not in
-// the shell gives +0 and hit = false.  Same arithmetic as tri_u.
-//
-// Inside = true: every sample of the shell lies in [0, n-2] on each axis, so the
-// clamps of tri_u are the identity, floor is truncation and the fraction is
-// exact as v_fract.  A sample's distance to the grid centre differs from the
-// atom's radius by FP32 rounding only (~1e-4 cells, against kShellPad), so by
-// construction of the band its row lies in the table and its cell in the row's
-// segment on its side of the centre (two separate segments are more than a cell
-// apart); the row and column indices are only clamped to keep reads in bounds.
-// Inside = false checks the row range and the segment, and reports misses.
-template <bool Inside>
+// Trilinear sample of grid coordinates (gx,gy,gz) from the shell, for an atom
+// whose sphere may leave the grid: the clamps of tri_u, the row range and the
+// segment are checked, and a cell not in the shell gives +0 and hit = false.
+// Same arithmetic as tri_u.
 __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, float gx, float gy,
                                               float gz, bool &hit) {
-    if (Inside) {
-        const float fx = __builtin_amdgcn_fractf(gx), fy = __builtin_amdgcn_fractf(gy),
-                    fz = __builtin_amdgcn_fractf(gz);
-        // absolute row iy*thz + iz, clamped to the table's rows [koff, koff+rows)
-        const unsigned ra = __umul24((unsigned)(int)gy, (unsigned)s.thz) + (unsigned)(int)gz;
-        const unsigned ri = min(max(ra, s.koff), s.klast);
-        const int2 e2 = s.table0[ri];
-        const int e = gx < s.cx ? e2.x : e2.y;
-        // the band holds the sample's cell by construction: no range test, only a
-        // clamp that keeps the read inside the band's columns
-        const int c = min((int)((unsigned)e & 0xFFFFu) - kEntryBias + (int)gx, s.maxcol);
-        hit = true;
-        return lerp_cell(s.col + c, fx, fy, fz);
-    }
     const float cx = __builtin_amdgcn_fmed3f(gx, 0.0f, t.mx);
     const float cy = __builtin_amdgcn_fmed3f(gy, 0.0f, t.my);
     const float cz = __builtin_amdgcn_fmed3f(gz, 0.0f, t.mz);
@@ -1276,10 +1253,15 @@ __device__ __forceinline__ float shell_sample(const Shell &s, const Tri &t, floa
 // in phases so that a wave keeps every sample's reads in flight together:
 // fractions and row entries, then the cell columns (LDS band, or the cube in
 // global memory for the slots is_global_slot picks), then the blends.  Each
-// value is the one shell_sample<true> or tri_in gives: fy is the fraction of gy
-// and rowy the byte address of row (int) gy * thz of the table (both per atom);
-// the row and column indices are those of shell_sample<true>, clamped the same
-// way, computed as LDS byte addresses.
+// value is the one tri_in gives.  Every sample lies in [0, n-2] on each axis, so
+// the clamps of tri_u are the identity, floor is truncation and the fraction is
+// exact as v_fract.  A sample's distance to the grid centre differs from the
+// atom's radius by FP32 rounding only (~1e-4 cells, against kShellPad), so by
+// construction of the band its row lies in the table and its cell in the row's
+// segment on its side of the centre (two separate segments are more than a cell
+// apart): the row and column indices are only clamped, to keep reads in bounds.
+// fy is the fraction of gy and rowy the byte address of row (int) gy * thz of
+// the table (both per atom); the indices are LDS byte addresses.
 template <int JM>
 __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, const Shell &s,
                                                const Tri &t, const float (&gx)[kShellBatch],
@@ -1335,7 +1317,7 @@ template <int JM, bool Inside>
 __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, const Tri &tr,
                                            const XStage &xs, cfloat2_p cj, int jw, float ex,
                                            float ez, int to) {
-    if (Inside) {
+    if constexpr (Inside) {
         const float fy = __builtin_amdgcn_fractf(xs.gy);
         const uint32_t rowy = shell_rowy(sh, xs.gy);
 #pragma unroll
@@ -1357,7 +1339,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
 #pragma unroll
         for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
         return;
-    }
+    } else {
     bool miss = false;
 #pragma unroll
     for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
@@ -1367,10 +1349,10 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
                 const float2 c = ld_cs(cj, jj);
                 const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
                 if (is_global_slot(JM, jj)) {
-                    acc[jj] += Inside ? tri_in(tr, gx, xs.gy, gz, to) : tri_u(tr, gx, xs.gy, gz, to);
+                    acc[jj] += tri_u(tr, gx, xs.gy, gz, to);
                 } else {
                     bool hit;
-                    acc[jj] += shell_sample<Inside>(sh, tr, gx, xs.gy, gz, hit);
+                    acc[jj] += shell_sample(sh, tr, gx, xs.gy, gz, hit);
                     miss = miss || !hit;
                 }
             }
@@ -1382,7 +1364,7 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
     // below and keeps every sample's inputs live)
 #pragma unroll
     for (int jj = 0; jj < JM; ++jj) asm volatile("" : "+v"(acc[jj]));
-    if (!Inside && __ballot(miss) != 0ull) {
+    if (__ballot(miss) != 0ull) {
         // recompute rather than keep the first pass's coordinates live across it
         // (an opaque zero offset stops the compiler merging the two passes)
         int z = 0;
@@ -1393,9 +1375,10 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
             const float2 c = ld_cs(cj, jj + z);
             const float gx = align_gx(xs, c, ex), gz = align_gz(xs, c, ez);
             bool hit;
-            (void)shell_sample<Inside>(sh, tr, gx, xs.gy, gz, hit);
+            (void)shell_sample(sh, tr, gx, xs.gy, gz, hit);
             if (!hit) acc[jj] += tri_u(tr, gx, xs.gy, gz, to);
         }
+    }
     }
 }
 
@@ -1684,9 +1667,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.maxcol = c0.y - c1.z - 2;  // last column pair of the band
                         sh.cx = g.acx;
                         sh.koff = (unsigned)(c0.z * c1.y + c0.w);
-                        sh.klast = sh.koff + (unsigned)(sh.rows - 1);
                         sh.table = (const int2 *)(region + offA);
-                        sh.table0 = sh.table - sh.koff;
                         sh.col = region + offA + c1.z;
                         sh.zero = zero2;
                         sh.zerob = zero_b;
@@ -1746,9 +1727,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                         sh.maxcol = c0.y - c1.z - 2;
                         sh.cx = g.acx;
                         sh.koff = (unsigned)(c0.z * c1.y + c0.w);
-                        sh.klast = sh.koff + (unsigned)(sh.rows - 1);
                         sh.table = (const int2 *)region;
-                        sh.table0 = sh.table - sh.koff;
                         sh.col = region + c1.z - C1;  // column c >= C1 at region + c1.z + (c - C1)
                         sh.zero = zero2;
                         sh.zerob = zero_b;
