@@ -1281,6 +1281,8 @@ __device__ __forceinline__ void shell_batch_in(float (&v)[kShellBatch], int j0, 
             e2[k] = lds_ld_int2(med3_u32(rowy + ((uint32_t)(int)gz[k] << 3), s.tlob, s.thib));
         }
     }
+    // every row read is issued before the first column address waits for one
+    __builtin_amdgcn_sched_barrier(0);
     float4 q0[kShellBatch], q1[kShellBatch];
 #pragma unroll
     for (int k = 0; k < kShellBatch; ++k) {
@@ -1612,7 +1614,7 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
             const int rr = sv ? rem : 0;  // padding lanes repeat the part's first strip
             const int gg = rr / A, i = rr - gg * A, j0 = part * JM;
             const bool won = sampler && wbase < strips;
-            const int jw = min(JM, A - j0);
+            const int jw_part = min(JM, A - j0);
             const int r = rbase + gg < sa.R ? rbase + gg : rbase;
             const float4 m0 = sa.smat[3 * r + 0], m1 = sa.smat[3 * r + 1], m2 = sa.smat[3 * r + 2];
             const float4 cw = ectr[2 * gg], ce = ectr[2 * gg + 1];
@@ -1651,6 +1653,10 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                 if (won) {
                     const float4 d = dxyz[a];
                     const int to = uniform_int(__float_as_int(d.w));
+                    // the batch tests j0 < jw are made here, per atom, in scalar
+                    // registers (hoisted out of the atom loop they are spilled)
+                    int jw = jw_part;
+                    asm volatile("" : "+s"(jw));
                     // start-pose offset of this atom for the lane's restart
                     const float yx = fmaf(m0.x, d.x, fmaf(m0.y, d.y, fmaf(m0.z, d.z, g.cx)));
                     const float yy = fmaf(m1.x, d.x, fmaf(m1.y, d.y, fmaf(m1.z, d.z, g.cy)));
@@ -1713,6 +1719,8 @@ __global__ __launch_bounds__(1024) void k_align(GridArgs g, SearchArgs sa, LibAr
                     __syncthreads();
                     if (won) {
                         const float4 d = dxyz[a];
+                        int jw = jw_part;
+                        asm volatile("" : "+s"(jw));
                         const float yx = fmaf(m0.x, d.x, fmaf(m0.y, d.y, fmaf(m0.z, d.z, g.cx)));
                         const float yy = fmaf(m1.x, d.x, fmaf(m1.y, d.y, fmaf(m1.z, d.z, g.cy)));
                         const float yz = fmaf(m2.x, d.x, fmaf(m2.y, d.y, fmaf(m2.z, d.z, g.cz)));
