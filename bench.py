@@ -41,14 +41,14 @@ PEAK_FP32_NONPACKED_TFLOPS = 78.6  # one wave64 FMA per CU per clock (packed FP3
 TRAFFIC = {
     # large batched workload, T=256: rocprofv3 FETCH_SIZE / WRITE_SIZE of k_align (all bins),
     # one step, scaled by the 256 MiB reference copy (factors 2.0 and 1.0)
-    (3, 256, 200000): ("k_align", "0a0ccdb21c872c14", 9.2922e+11),
+    (3, 256, 200000): ("k_align", "a5b39e79a4970aea", 9.2916e+11),
 }
 
 # VALU wave-instructions per step of all docking kernels (rocprofv3 SQ_INSTS_VALU, one
 # step), for the VALU-instruction roofline: one wave64 VALU instruction per CU per
 # clock, 256 CUs at 2.4 GHz.  Same validity rule as TRAFFIC: (source sha, instructions).
 VALU_INSTR = {
-    (3, 256, 200000): ("0a0ccdb21c872c14", 3.2912e+12),
+    (3, 256, 200000): ("a5b39e79a4970aea", 3.2905e+12),
 }
 VALU_ROOF_PER_S = 256 * 2.4e9
 

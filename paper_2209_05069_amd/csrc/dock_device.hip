@@ -1322,15 +1322,25 @@ __device__ __forceinline__ void shell_atom(float (&acc)[JM], const Shell &sh, co
     if constexpr (Inside) {
         const float fy = __builtin_amdgcn_fractf(xs.gy);
         const uint32_t rowy = shell_rowy(sh, xs.gy);
+        // (cos, sin) of the next batch's y rotations, loaded one batch ahead
+        float2 cn[kShellBatch];
+#pragma unroll
+        for (int k = 0; k < kShellBatch; ++k) cn[k] = ld_cs(cj, k);
 #pragma unroll
         for (int j0 = 0; j0 < JM; j0 += kShellBatch) {
             if (j0 < jw) {
                 float gx[kShellBatch], gz[kShellBatch], v[kShellBatch];
+                float2 cc[kShellBatch];
+#pragma unroll
+                for (int k = 0; k < kShellBatch; ++k) cc[k] = cn[k];
+                if (j0 + kShellBatch < JM) {
+#pragma unroll
+                    for (int k = 0; k < kShellBatch; ++k) cn[k] = ld_cs(cj, j0 + kShellBatch + k);
+                }
 #pragma unroll
                 for (int k = 0; k < kShellBatch; ++k) {
-                    const float2 c = ld_cs(cj, j0 + k);
-                    gx[k] = align_gx(xs, c, ex);
-                    gz[k] = align_gz(xs, c, ez);
+                    gx[k] = align_gx(xs, cc[k], ex);
+                    gz[k] = align_gz(xs, cc[k], ez);
                 }
                 shell_batch_in<JM>(v, j0, sh, tr, gx, xs.gy, fy, rowy, gz, to);
 #pragma unroll
