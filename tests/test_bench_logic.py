@@ -90,3 +90,24 @@ def test_valu_instructions_only_for_the_measured_source_and_workload():
     finally:
         bench.VALU_INSTR.clear()
         bench.VALU_INSTR.update(saved)
+
+
+def test_counter_figures_match_the_committed_profile():
+    """The byte and VALU-instruction counts bench.py reports for the large batched
+    workload are the ones of the committed rocprofv3 summary, taken on the kernel
+    source that summary names."""
+    import re
+    text = open(os.path.join(ROOT, "profiles",
+                             "k_align_k_dock_c3_trace_counters_bytes.md")).read()
+    sha = re.search(r"Kernel source sha256 prefix:\s*`([0-9a-f]{16})`", text).group(1)
+    nbytes = float(re.search(r"k_align \(the dominant kernel\): ([0-9.e+]+) bytes per step",
+                             text).group(1))
+    valu = float(re.search(r"roofline of the whole step: ([0-9.e+]+) VALU wave-instructions",
+                           text).group(1))
+    L3 = synth.CONFIGS[3]["ligands"]["L"]
+    kernel, tsha, tbytes = bench.TRAFFIC[(3, 256, L3)]
+    vsha, vcount = bench.VALU_INSTR[(3, 256, L3)]
+    assert kernel == "k_align"
+    assert tsha == sha and vsha == sha
+    assert tbytes == pytest.approx(nbytes, rel=1e-4)
+    assert vcount == pytest.approx(valu, rel=1e-4)
